@@ -1,0 +1,159 @@
+/*
+ * tor.h -- C ABI of the MI355X Torontonian library.
+ *
+ * The library evaluates the Torontonian (Sec. 3.1, Eq. 2 of "Benchmarking
+ * 50-Photon Gaussian Boson Sampling on the Sunway TaihuLight"):
+ *
+ *     Tor(O) = sum over Z subset of {1..n} of (-1)^(n-|Z|) / sqrt(det(I - O_Z)),
+ *
+ * where O is the 2n x 2n sampling matrix of an n-click pattern (Eq. 1: the
+ * paper's A_{S}, with A = I - Sigma^{-1}) and O_Z keeps rows and columns i
+ * and i+n for every i in Z.  It is the probability of the click pattern
+ * divided by the vacuum probability (Eq. 1), so GBS samplers need many of
+ * them.
+ *
+ * Conventions for every entry point:
+ *   - O is complex128 (interleaved re, im), row-major, leading dimension
+ *     `ld` >= 2n in complex elements, in the paper's block order
+ *     [[O00, O01], [O10, O11]] (all a-modes, then all a^dagger-modes).
+ *   - Only the lower triangle (row >= column) is read.  The input must be
+ *     exactly Hermitian, with I - O positive definite (then every I - O_Z
+ *     is, Sec. 4.2); a pivot that is not > 0 is reported as TOR_ENOTPD.
+ *   - n = 0 gives Tor = 1 (the empty set is the one term).
+ *   - Pointers marked "device" are HIP device pointers; the caller owns all
+ *     input and output buffers.  The library owns a per-device workspace,
+ *     allocated on first use and released by tor_shutdown().
+ *   - `stream` is a hipStream_t (NULL: the default stream).  Work is
+ *     enqueued on it; synchronous entry points also wait for it.
+ *   - Every call returns TOR_OK (0) or a negative TOR_E* code; nothing
+ *     throws or aborts across the ABI.  Calls on one device are not
+ *     thread-safe with respect to each other.
+ */
+#ifndef TOR_H
+#define TOR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Error codes. */
+#define TOR_OK 0
+#define TOR_EINVAL (-1)       /* n out of range, null pointer, bad ld, unknown tier/algo */
+#define TOR_ENOTPD (-2)       /* a pivot was not > 0: I - O is not positive definite */
+#define TOR_EHIP (-3)         /* a HIP runtime error */
+#define TOR_ENOMEM (-4)       /* device allocation failed */
+#define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan */
+
+/* Largest n accepted (subset masks are 64-bit; factor storage in LDS). */
+#define TOR_NMAX 48
+
+/* Precision tiers (Sec. 5.1-5.4; the paper's 128-bit tier corresponds to
+ * TOR_DD and its 256-bit tier to TOR_QD, as in Table 5). */
+typedef enum {
+  TOR_FP64 = 0, /* binary64 arithmetic, double-double accumulation of terms */
+  TOR_DD = 1,   /* double-double (~106-bit significand) throughout */
+  TOR_QD = 2,   /* quad-double (~212-bit significand) throughout */
+  TOR_AUTO = -1 /* the library picks per instance (precision selector) */
+} tor_tier_t;
+
+/* Subset-tree algorithms.  Both enumerate the 2^n subsets as depth-first
+ * subtrees hanging off prefixes of the first d modes (Sec. 4.1 splits the
+ * same enumeration by subset size instead) and carry one factorisation
+ * along each path. */
+typedef enum {
+  TOR_ALGO_AUTO = 0,
+  TOR_ALGO_BORDER = 1 /* bordered Cholesky: appending a mode adds two rows to
+                         the factor, O(|Z|^2) per subset (Sec. 4.2's
+                         elimination made incremental) */
+} tor_algo_t;
+
+/* Result of one Torontonian. 64 bytes. */
+typedef struct tor_result {
+  double tor[4];     /* Tor as a non-overlapping expansion, largest first:
+                        FP64 and DD fill [0..1], QD fills [0..3]; rest 0 */
+  double abs_sum[2]; /* S_abs = sum of |terms|, double-double; the
+                        cancellation ratio is abs_sum / |tor| */
+  double err_bound;  /* a-priori estimate of |Tor - computed| (absolute):
+                        c * (2n)^2 * u_tier * S_abs */
+  int32_t tier_used; /* tier the value was computed in */
+  int32_t status;    /* TOR_OK or TOR_ENOTPD for this instance */
+} tor_result_t;
+
+/* Optional knobs; pass NULL for defaults. */
+typedef struct tor_options {
+  int32_t algo;        /* tor_algo_t */
+  int32_t split_depth; /* d: number of leading modes whose subsets form the
+                          work items (2^d of them); -1 = autotuned */
+  int32_t grid;        /* persistent workgroups; 0 = from occupancy */
+  int32_t reserved;
+} tor_options_t;
+
+/* Library version string. */
+const char* tor_version(void);
+
+/* Text for an error code. */
+const char* tor_strerror(int code);
+
+/* Optional: set up the workspace of the current device ahead of time. */
+int tor_init(void);
+
+/* Release the workspaces of all devices (the library re-creates them on
+ * the next call). */
+int tor_shutdown(void);
+
+/* Tor(O) for one instance (Sec. 3.1, Eq. 2).
+ *   O      device, complex128, 2n x 2n, block order, lower triangle read
+ *   n      0 <= n <= TOR_NMAX
+ *   ld     leading dimension of O in complex elements (>= 2n)
+ *   tier   TOR_FP64, TOR_DD or TOR_QD
+ *   opt    NULL or knobs
+ *   stream hipStream_t or NULL
+ *   out    host; filled on return
+ * Synchronous: enqueues on `stream` and waits for it. */
+int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_options_t* opt,
+             void* stream, tor_result_t* out);
+
+/* Per-level sums L_m = sum over |Z| = m of det(I - O_Z)^(-1/2), m = 0..n
+ * (the pieces Alg. 1's level loop adds up, each unsigned).
+ *   out_levels  host, 4*(n+1) doubles: level m as an expansion at [4m..4m+3]
+ *   out         host, the Torontonian of the same run
+ * Synchronous. */
+int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
+                         double* out_levels, tor_result_t* out);
+
+/* det(I - O_Z)^(-1/2) with its sign (-1)^(n-|Z|) for k explicit subsets
+ * (one term of Eq. 2 each).
+ *   masks      device, k uint64 (bit i <=> mode i in Z, i < n)
+ *   out_terms  device, 4*k doubles: term i as an expansion at [4i..4i+3]
+ * Enqueued on `stream`; returns without waiting. */
+int tor_debug_sampled_terms(const void* O, int32_t n, int64_t ld, int32_t tier,
+                            const uint64_t* masks, int64_t k, void* stream, double* out_terms);
+
+/* ---- Host-side scheduling helpers (no GPU needed) ----------------------
+ * Alg. 2's mask functions, used to order the work items by subset size. */
+
+/* Next N-bit mask with the same number of ones, in decreasing numeric order
+ * (Alg. 2, get_next_mask: the trailing block of ones moves down under the
+ * lowest remaining one).  Returns 0 after the last mask of that popcount. */
+uint64_t tor_next_mask(uint64_t mask);
+
+/* The k-th (0-based) N-bit mask with c ones, in the same decreasing order
+ * (Alg. 2, get_kth_mask: bits decided from the top, skipping blocks of
+ * C(remaining positions, remaining ones) masks).  N <= 63, 0 <= c <= N,
+ * k < C(N, c); returns 0 for out-of-range arguments. */
+uint64_t tor_kth_mask(int32_t N, int32_t c, uint64_t k);
+
+/* The 2^d work items of an n-mode evaluation split at depth d: every subset
+ * of modes [0, d) exactly once, largest subsets first (their subtrees carry
+ * the largest factors), each size class in decreasing numeric order.
+ *   out   host, 2^d uint64
+ * 0 <= d <= min(n, 30). */
+int tor_plan_items(int32_t n, int32_t d, uint64_t* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOR_H */

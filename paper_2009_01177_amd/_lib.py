@@ -1,0 +1,101 @@
+"""ctypes loader for libtor_hip.so (argument marshalling only).
+
+The library is built in-tree by paper_2009_01177_amd.build.  There is no
+fallback: if the shared library is missing or fails to load, every call
+raises, so no result can silently come from anywhere but the HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtor_hip.so")
+
+TOR_OK, TOR_EINVAL, TOR_ENOTPD, TOR_EHIP, TOR_ENOMEM, TOR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO = 0, 1, 2, -1
+TOR_ALGO_AUTO, TOR_ALGO_BORDER = 0, 1
+TOR_NMAX = 48
+
+# Every symbol include/tor.h declares.
+EXPORTS = (
+    "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval",
+    "tor_debug_level_sums", "tor_debug_sampled_terms",
+    "tor_next_mask", "tor_kth_mask", "tor_plan_items",
+)
+
+
+class TorResultC(ctypes.Structure):
+    _fields_ = [
+        ("tor", ctypes.c_double * 4),
+        ("abs_sum", ctypes.c_double * 2),
+        ("err_bound", ctypes.c_double),
+        ("tier_used", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class TorOptionsC(ctypes.Structure):
+    _fields_ = [
+        ("algo", ctypes.c_int32),
+        ("split_depth", ctypes.c_int32),
+        ("grid", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class TorError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _strerror(code)
+        super().__init__(f"{what}: {msg} ({code})" if what else f"{msg} ({code})")
+
+
+_lib = None
+
+
+def _strerror(code: int) -> str:
+    try:
+        return lib().tor_strerror(code).decode()
+    except Exception:  # pragma: no cover - only when the library is absent
+        return "error %d" % code
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libtor_hip.so is not built (run `python -m paper_2009_01177_amd.build` "
+            "or __graft_entry__.build())")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.tor_version.restype = ctypes.c_char_p
+    L.tor_strerror.restype = ctypes.c_char_p
+    L.tor_strerror.argtypes = [ctypes.c_int]
+    L.tor_init.restype = ctypes.c_int
+    L.tor_shutdown.restype = ctypes.c_int
+    L.tor_eval.restype = ctypes.c_int
+    L.tor_eval.argtypes = [vp, i32, i64, i32, ctypes.POINTER(TorOptionsC), vp,
+                           ctypes.POINTER(TorResultC)]
+    L.tor_debug_level_sums.restype = ctypes.c_int
+    L.tor_debug_level_sums.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
+    L.tor_debug_sampled_terms.restype = ctypes.c_int
+    L.tor_debug_sampled_terms.argtypes = [vp, i32, i64, i32, vp, i64, vp, vp]
+    L.tor_next_mask.restype = u64
+    L.tor_next_mask.argtypes = [u64]
+    L.tor_kth_mask.restype = u64
+    L.tor_kth_mask.argtypes = [i32, i32, u64]
+    L.tor_plan_items.restype = ctypes.c_int
+    L.tor_plan_items.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_uint64)]
+    _lib = L
+    return L
+
+
+def check(code: int, what: str = "") -> int:
+    if code != TOR_OK:
+        raise TorError(code, what)
+    return code

@@ -1,0 +1,164 @@
+"""Python binding of the C ABI (include/tor.h), same names, argument
+marshalling only.  PyTorch provides device memory and the current stream;
+every step of the evaluation runs in the library's HIP kernels."""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass, field
+from fractions import Fraction
+
+import numpy as np
+
+from . import _lib
+from ._lib import TorError, check, lib
+
+_TIERS = {"fp64": _lib.TOR_FP64, "dd": _lib.TOR_DD, "qd": _lib.TOR_QD, "auto": _lib.TOR_AUTO}
+_ALGOS = {"auto": _lib.TOR_ALGO_AUTO, "border": _lib.TOR_ALGO_BORDER}
+
+
+def tier_id(tier) -> int:
+    if isinstance(tier, str):
+        return _TIERS[tier.lower()]
+    return int(tier)
+
+
+def algo_id(algo) -> int:
+    if isinstance(algo, str):
+        return _ALGOS[algo.lower()]
+    return int(algo)
+
+
+@dataclass
+class TorResult:
+    expansion: tuple          # Tor as (hi, lo, ...) non-overlapping doubles
+    abs_sum: tuple            # S_abs as double-double
+    err_bound: float
+    tier_used: int
+    status: int
+    value: float = field(init=False)
+
+    def __post_init__(self):
+        self.value = float(sum(Fraction(x) for x in self.expansion))
+
+    @property
+    def exact(self) -> Fraction:
+        """The returned expansion summed exactly."""
+        return sum((Fraction(x) for x in self.expansion), Fraction(0))
+
+    @property
+    def abs_exact(self) -> Fraction:
+        return sum((Fraction(x) for x in self.abs_sum), Fraction(0))
+
+    @property
+    def kappa(self) -> float:
+        t = self.exact
+        return float(self.abs_exact / abs(t)) if t != 0 else float("inf")
+
+
+def _res(r: _lib.TorResultC) -> TorResult:
+    return TorResult(tuple(r.tor), tuple(r.abs_sum), r.err_bound, r.tier_used, r.status)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _device_o(O):
+    """complex128 device tensor (contiguous rows) and n, ld."""
+    torch = _torch()
+    if isinstance(O, np.ndarray):
+        O = torch.from_numpy(np.ascontiguousarray(O, dtype=np.complex128))
+    if not isinstance(O, torch.Tensor):
+        raise TypeError("O must be a numpy array or a torch tensor")
+    if O.dtype != torch.complex128:
+        O = O.to(torch.complex128)
+    if not O.is_cuda:
+        O = O.to("cuda")
+    if O.dim() != 2 or O.shape[0] != O.shape[1] or O.shape[0] % 2:
+        raise ValueError("O must be 2n x 2n")
+    if O.stride(1) != 1:
+        O = O.contiguous()
+    n = O.shape[0] // 2
+    ld = O.stride(0) if n > 0 else 0
+    return O, n, max(ld, 2 * n)
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def tor_version() -> str:
+    return lib().tor_version().decode()
+
+
+def tor_init():
+    check(lib().tor_init(), "tor_init")
+
+
+def tor_shutdown():
+    check(lib().tor_shutdown(), "tor_shutdown")
+
+
+def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
+             stream=None, raise_on_error: bool = True) -> TorResult:
+    """Tor(O) of one instance (synchronous)."""
+    Od, n, ld = _device_o(O)
+    opt = _lib.TorOptionsC(algo_id(algo), int(split_depth), int(grid), 0)
+    out = _lib.TorResultC()
+    rc = lib().tor_eval(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), ctypes.byref(opt),
+                        _stream_ptr(stream), ctypes.byref(out))
+    if rc != _lib.TOR_OK and raise_on_error:
+        raise TorError(rc, "tor_eval")
+    return _res(out)
+
+
+def tor_debug_level_sums(O, tier="dd", stream=None):
+    """(levels, result): levels[m] is L_m = sum over |Z| = m of det^(-1/2),
+    each as a Fraction of the returned expansion."""
+    Od, n, ld = _device_o(O)
+    lv = np.zeros(4 * (n + 1), dtype=np.float64)
+    out = _lib.TorResultC()
+    rc = lib().tor_debug_level_sums(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier),
+                                    _stream_ptr(stream),
+                                    lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    ctypes.byref(out))
+    check(rc, "tor_debug_level_sums")
+    levels = [sum((Fraction(x) for x in lv[4 * m:4 * m + 4]), Fraction(0)) for m in range(n + 1)]
+    return levels, _res(out)
+
+
+def tor_debug_sampled_terms(O, masks, tier="dd", stream=None) -> np.ndarray:
+    """Signed terms of the given subsets: array (k, 4) of expansions."""
+    torch = _torch()
+    Od, n, ld = _device_o(O)
+    m = torch.as_tensor(np.ascontiguousarray(np.asarray(masks, dtype=np.uint64)).view(np.int64),
+                        device=Od.device)
+    k = m.numel()
+    out = torch.zeros((k, 4), dtype=torch.float64, device=Od.device)
+    rc = lib().tor_debug_sampled_terms(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier),
+                                       ctypes.c_void_p(m.data_ptr()), k, _stream_ptr(stream),
+                                       ctypes.c_void_p(out.data_ptr()))
+    check(rc, "tor_debug_sampled_terms")
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return out.cpu().numpy()
+
+
+# ---- host scheduling helpers (no GPU) -------------------------------------
+
+def tor_next_mask(mask: int) -> int:
+    return int(lib().tor_next_mask(int(mask)))
+
+
+def tor_kth_mask(N: int, c: int, k: int) -> int:
+    return int(lib().tor_kth_mask(int(N), int(c), int(k)))
+
+
+def tor_plan_items(n: int, d: int) -> np.ndarray:
+    out = np.zeros(1 << d, dtype=np.uint64)
+    check(lib().tor_plan_items(int(n), int(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),
+          "tor_plan_items")
+    return out

@@ -1,0 +1,301 @@
+// prec.hpp -- extended precision built from binary64 error-free transforms.
+//
+// The paper runs the Torontonian in 128- and 256-bit fixed point (Sec. 5.2,
+// 5.3) because binary64 cannot hold the ~25 significant digits that the
+// alternating sum needs (Sec. 5.1).  This library instead builds floating
+// tiers on binary64 hardware, the same pairing Table 5 makes between the
+// 128-bit tier and double-double (106 bits) and the 256-bit tier and
+// quad-double (212 bits):
+//
+//   F64  plain binary64 with fused multiply-add;
+//   DD   double-double  (hi + lo, |lo| <= ulp(hi)/2);
+//   QD   quad-double    (x0 + x1 + x2 + x3, a non-overlapping expansion).
+//
+// Error-free transforms (round to nearest-even, no reassociation, no
+// contraction: this file must be compiled with -ffp-contract=off and
+// without fast-math):
+//   two_sum       Knuth: s + e == a + b exactly.
+//   fast_two_sum  Dekker: same, valid when |a| >= |b| or a == 0.
+//   two_prod      p + e == a * b exactly, e = fma(a, b, -p).
+//
+// Double-double operations follow Joldes, Muller and Popescu, "Tight and
+// rigorous error bounds for basic building blocks of double-word arithmetic"
+// (ACM TOMS 2017): DWPlusFP, AccurateDWPlusDW, DWTimesFP (FMA form) and
+// DWTimesDW (FMA form), with relative error bounds 2u^2, 3u^2 + 13u^3, 2u^2
+// and 4u^2 (u = 2^-53).  Reciprocal, square root and reciprocal square root
+// take one Newton step from the binary64 approximation with the residual
+// formed in double-double.
+//
+// Quad-double values are kept as 4-term expansions.  Every operation forms
+// an exact multi-term intermediate (with two_sum / two_prod) and compresses
+// it back to four terms by repeated distillation: a bottom-up chain of
+// two_sums yields the rounded total and the exact list of its rounding
+// errors; the chain is run again on those errors to give the next term, and
+// so on four times.  The value kept differs from the exact intermediate by
+// about u^4 of the sum of the magnitudes involved.  This is branch-free,
+// which suits 64-wide wavefronts.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define PREC_HD __host__ __device__ __forceinline__
+#else
+#define PREC_HD inline
+#endif
+
+namespace prec {
+
+// ---------------------------------------------------------------------------
+// Error-free transforms
+// ---------------------------------------------------------------------------
+
+PREC_HD void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+PREC_HD void fast_two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  e = b - (s - a);
+}
+
+PREC_HD void two_prod(double a, double b, double& p, double& e) {
+  p = a * b;
+  e = fma(a, b, -p);
+}
+
+// ---------------------------------------------------------------------------
+// Double-double
+// ---------------------------------------------------------------------------
+
+struct dd {
+  double hi, lo;
+};
+
+PREC_HD dd dd_make(double x) { return dd{x, 0.0}; }
+
+PREC_HD dd dd_neg(dd a) { return dd{-a.hi, -a.lo}; }
+
+// DWPlusFP
+PREC_HD dd dd_add_d(dd a, double b) {
+  double sh, sl;
+  two_sum(a.hi, b, sh, sl);
+  double v = a.lo + sl;
+  dd z;
+  fast_two_sum(sh, v, z.hi, z.lo);
+  return z;
+}
+
+// AccurateDWPlusDW
+PREC_HD dd dd_add(dd x, dd y) {
+  double sh, sl, th, tl;
+  two_sum(x.hi, y.hi, sh, sl);
+  two_sum(x.lo, y.lo, th, tl);
+  double c = sl + th;
+  double vh, vl;
+  fast_two_sum(sh, c, vh, vl);
+  double w = tl + vl;
+  dd z;
+  fast_two_sum(vh, w, z.hi, z.lo);
+  return z;
+}
+
+PREC_HD dd dd_sub(dd x, dd y) { return dd_add(x, dd_neg(y)); }
+
+// DWTimesFP (FMA form)
+PREC_HD dd dd_mul_d(dd x, double y) {
+  double ch, cl1;
+  two_prod(x.hi, y, ch, cl1);
+  double cl3 = fma(x.lo, y, cl1);
+  dd z;
+  fast_two_sum(ch, cl3, z.hi, z.lo);
+  return z;
+}
+
+// DWTimesDW (FMA form)
+PREC_HD dd dd_mul(dd x, dd y) {
+  double ch, cl1;
+  two_prod(x.hi, y.hi, ch, cl1);
+  double tl0 = x.lo * y.lo;
+  double tl1 = fma(x.hi, y.lo, tl0);
+  double cl2 = fma(x.lo, y.hi, tl1);
+  double cl3 = cl1 + cl2;
+  dd z;
+  fast_two_sum(ch, cl3, z.hi, z.lo);
+  return z;
+}
+
+// Exact product of two binary64 values as a double-double.
+PREC_HD dd dd_prod_dd(double a, double b) {
+  dd z;
+  two_prod(a, b, z.hi, z.lo);
+  return z;
+}
+
+// 1/y: Newton step r1 = r0 + r0 (1 - y r0), residual in double-double.
+PREC_HD dd dd_recip(dd y) {
+  double r0 = 1.0 / y.hi;
+  // e = 1 - y*r0: 1 - yh*r0 is exact through fma; subtract yl*r0.
+  double eh = fma(-y.hi, r0, 1.0);
+  double e = eh - y.lo * r0;
+  dd z;
+  fast_two_sum(r0, r0 * e, z.hi, z.lo);
+  return z;
+}
+
+PREC_HD dd dd_div(dd x, dd y) {
+  // q0 = x.hi / y.hi; remainder x - y*q0 in double-double; one correction.
+  double q0 = x.hi / y.hi;
+  dd p = dd_mul_d(y, q0);
+  dd r = dd_sub(x, p);
+  double q1 = r.hi / y.hi;
+  dd z;
+  fast_two_sum(q0, q1, z.hi, z.lo);
+  return z;
+}
+
+// sqrt: s1 = s0 + (x - s0^2) / (2 s0), with s0^2 exact through two_prod.
+PREC_HD dd dd_sqrt(dd x) {
+  if (!(x.hi > 0.0)) return dd{x.hi == 0.0 ? 0.0 : sqrt(x.hi), 0.0};
+  double s0 = sqrt(x.hi);
+  double p, e;
+  two_prod(s0, s0, p, e);
+  double r = ((x.hi - p) - e) + x.lo;
+  dd z;
+  fast_two_sum(s0, r * (0.5 / s0), z.hi, z.lo);
+  return z;
+}
+
+// 1/sqrt(x): y1 = y0 + y0 (1 - x y0^2) / 2, x y0^2 in double-double.
+PREC_HD dd dd_rsqrt(dd x) {
+  double y0 = 1.0 / sqrt(x.hi);
+  dd y2 = dd_prod_dd(y0, y0);
+  dd xy2 = dd_mul(x, y2);
+  // h = 1 - xy2; xy2 is within a few ulps of 1, so 1 - xy2.hi is exact.
+  double h = (1.0 - xy2.hi) - xy2.lo;
+  dd z;
+  fast_two_sum(y0, y0 * (0.5 * h), z.hi, z.lo);
+  return z;
+}
+
+PREC_HD double dd_to_d(dd a) { return a.hi + a.lo; }
+
+// ---------------------------------------------------------------------------
+// Quad-double
+// ---------------------------------------------------------------------------
+
+struct qd {
+  double x[4];
+};
+
+PREC_HD qd qd_make(double a) { return qd{{a, 0.0, 0.0, 0.0}}; }
+PREC_HD qd qd_from_dd(dd a) { return qd{{a.hi, a.lo, 0.0, 0.0}}; }
+PREC_HD qd qd_neg(qd a) { return qd{{-a.x[0], -a.x[1], -a.x[2], -a.x[3]}}; }
+
+// One distillation pass over t[0..k-1] (k >= 1), largest-expected first:
+// returns the rounded total; t[1..k-1] receive the exact rounding errors
+// (t[0] is left unspecified).  sum(before) == total + sum(t[1..k-1]) exactly.
+template <int K>
+PREC_HD double distill(double* t) {
+  double s = t[K - 1];
+#pragma unroll
+  for (int i = K - 2; i >= 0; --i) {
+    double e;
+    two_sum(t[i], s, s, e);
+    t[i + 1] = e;
+  }
+  return s;
+}
+
+// Compress an exact K-term list into a 4-term expansion.
+template <int K>
+PREC_HD qd qd_compress(double* t) {
+  qd r;
+  r.x[0] = distill<K>(t);
+  r.x[1] = distill<K - 1>(t + 1);
+  r.x[2] = distill<K - 2>(t + 2);
+  // the last term only needs the rounded total of what is left
+  double s = 0.0;
+#pragma unroll
+  for (int i = K - 1; i >= 3; --i) s += t[i];
+  r.x[3] = s;
+  return r;
+}
+
+PREC_HD qd qd_add(qd a, qd b) {
+  double t[8] = {a.x[0], b.x[0], a.x[1], b.x[1], a.x[2], b.x[2], a.x[3], b.x[3]};
+  return qd_compress<8>(t);
+}
+
+PREC_HD qd qd_sub(qd a, qd b) { return qd_add(a, qd_neg(b)); }
+
+PREC_HD qd qd_add_d(qd a, double b) {
+  double t[5] = {a.x[0], b, a.x[1], a.x[2], a.x[3]};
+  return qd_compress<5>(t);
+}
+
+PREC_HD qd qd_add_dd(qd a, dd b) {
+  double t[6] = {a.x[0], b.hi, a.x[1], b.lo, a.x[2], a.x[3]};
+  return qd_compress<6>(t);
+}
+
+PREC_HD qd qd_mul_d(qd a, double b) {
+  double t[8];
+  two_prod(a.x[0], b, t[0], t[1]);
+  two_prod(a.x[1], b, t[2], t[3]);
+  two_prod(a.x[2], b, t[4], t[5]);
+  t[6] = a.x[3] * b;
+  t[7] = 0.0;
+  return qd_compress<7>(t);
+}
+
+PREC_HD qd qd_mul(qd a, qd b) {
+  // products a_i b_j with i + j <= 2 exactly (two_prod), i + j == 3 rounded;
+  // the dropped part is below u^4 of |a b|.
+  double t[16];
+  two_prod(a.x[0], b.x[0], t[0], t[1]);
+  two_prod(a.x[0], b.x[1], t[2], t[4]);
+  two_prod(a.x[1], b.x[0], t[3], t[5]);
+  two_prod(a.x[0], b.x[2], t[6], t[9]);
+  two_prod(a.x[1], b.x[1], t[7], t[10]);
+  two_prod(a.x[2], b.x[0], t[8], t[11]);
+  t[12] = a.x[0] * b.x[3];
+  t[13] = a.x[1] * b.x[2];
+  t[14] = a.x[2] * b.x[1];
+  t[15] = a.x[3] * b.x[0];
+  return qd_compress<16>(t);
+}
+
+PREC_HD double qd_to_d(qd a) { return a.x[0] + (a.x[1] + (a.x[2] + a.x[3])); }
+
+// 1/y by Newton from the double-double reciprocal: r <- r + r (1 - y r).
+PREC_HD qd qd_recip(qd y) {
+  dd r0 = dd_recip(dd{y.x[0], y.x[1]});
+  qd r = qd_from_dd(r0);
+  qd e = qd_add_d(qd_neg(qd_mul(y, r)), 1.0);
+  return qd_add(r, qd_mul(r, e));
+}
+
+PREC_HD qd qd_div(qd x, qd y) { return qd_mul(x, qd_recip(y)); }
+
+// 1/sqrt(x) by Newton from double-double: y <- y + y (1 - x y^2) / 2.
+PREC_HD qd qd_rsqrt(qd x) {
+  dd y0 = dd_rsqrt(dd{x.x[0], x.x[1]});
+  qd y = qd_from_dd(y0);
+  qd h = qd_add_d(qd_neg(qd_mul(x, qd_mul(y, y))), 1.0);
+  return qd_add(y, qd_mul_d(qd_mul(y, h), 0.5));
+}
+
+// sqrt(x) = x * rsqrt(x), then one Newton correction s + (x - s^2)/(2s).
+PREC_HD qd qd_sqrt(qd x) {
+  if (!(x.x[0] > 0.0)) return qd_make(x.x[0] == 0.0 ? 0.0 : sqrt(x.x[0]));
+  qd r = qd_rsqrt(x);
+  qd s = qd_mul(x, r);
+  qd res = qd_add(x, qd_neg(qd_mul(s, s)));
+  return qd_add(s, qd_mul_d(qd_mul(res, r), 0.5));
+}
+
+}  // namespace prec

@@ -1,0 +1,213 @@
+// tiers.hpp -- device-side arithmetic for the three precision tiers, in one
+// interface the kernels are templated on.
+//
+//   tier F64: values binary64, fused multiply-add; subset terms accumulated
+//             in double-double.
+//   tier DD : values double-double; terms accumulated in double-double.
+//   tier QD : values quad-double; terms accumulated in quad-double.
+//
+// The staged input (-O in interleaved mode order) is binary64; entries of
+// I - O off the diagonal are exactly -O, and the diagonal 1 - O_ii is formed
+// exactly in DD and QD (two_sum) and rounded once in F64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "prec.hpp"
+
+namespace tor {
+
+using prec::dd;
+using prec::qd;
+
+template <class R>
+struct cx {
+  R re, im;
+};
+
+// --------------------------------------------------------------------------
+// Real operations per value type
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ double r_add(double a, double b) { return a + b; }
+__device__ __forceinline__ double r_sub(double a, double b) { return a - b; }
+__device__ __forceinline__ double r_mul(double a, double b) { return a * b; }
+__device__ __forceinline__ double r_neg(double a) { return -a; }
+__device__ __forceinline__ double r_from(double a) { return a; }
+__device__ __forceinline__ double r_lead(double a) { return a; }
+__device__ __forceinline__ double r_rsqrt(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ double r_one_minus(double o) { return 1.0 - o; }
+// c - a*b and c + a*b with one rounding
+__device__ __forceinline__ double r_fms(double c, double a, double b) { return fma(-a, b, c); }
+__device__ __forceinline__ double r_fma(double c, double a, double b) { return fma(a, b, c); }
+
+__device__ __forceinline__ dd r_add(dd a, dd b) { return prec::dd_add(a, b); }
+__device__ __forceinline__ dd r_sub(dd a, dd b) { return prec::dd_sub(a, b); }
+__device__ __forceinline__ dd r_mul(dd a, dd b) { return prec::dd_mul(a, b); }
+__device__ __forceinline__ dd r_neg(dd a) { return prec::dd_neg(a); }
+__device__ __forceinline__ double r_lead(dd a) { return a.hi; }
+__device__ __forceinline__ dd r_rsqrt(dd a) { return prec::dd_rsqrt(a); }
+__device__ __forceinline__ dd r_fms(dd c, dd a, dd b) { return prec::dd_sub(c, prec::dd_mul(a, b)); }
+__device__ __forceinline__ dd r_fma(dd c, dd a, dd b) { return prec::dd_add(c, prec::dd_mul(a, b)); }
+
+__device__ __forceinline__ qd r_add(qd a, qd b) { return prec::qd_add(a, b); }
+__device__ __forceinline__ qd r_sub(qd a, qd b) { return prec::qd_sub(a, b); }
+__device__ __forceinline__ qd r_mul(qd a, qd b) { return prec::qd_mul(a, b); }
+__device__ __forceinline__ qd r_neg(qd a) { return prec::qd_neg(a); }
+__device__ __forceinline__ double r_lead(qd a) { return a.x[0]; }
+__device__ __forceinline__ qd r_rsqrt(qd a) { return prec::qd_rsqrt(a); }
+__device__ __forceinline__ qd r_fms(qd c, qd a, qd b) { return prec::qd_sub(c, prec::qd_mul(a, b)); }
+__device__ __forceinline__ qd r_fma(qd c, qd a, qd b) { return prec::qd_add(c, prec::qd_mul(a, b)); }
+
+template <class R>
+__device__ __forceinline__ R r_zero();
+template <>
+__device__ __forceinline__ double r_zero<double>() { return 0.0; }
+template <>
+__device__ __forceinline__ dd r_zero<dd>() { return dd{0.0, 0.0}; }
+template <>
+__device__ __forceinline__ qd r_zero<qd>() { return qd{{0.0, 0.0, 0.0, 0.0}}; }
+
+template <class R>
+__device__ __forceinline__ R r_of(double x);
+template <>
+__device__ __forceinline__ double r_of<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ dd r_of<dd>(double x) { return dd{x, 0.0}; }
+template <>
+__device__ __forceinline__ qd r_of<qd>(double x) { return qd{{x, 0.0, 0.0, 0.0}}; }
+
+// 1 - o, exact in DD and QD
+template <class R>
+__device__ __forceinline__ R r_one_minus_t(double o);
+template <>
+__device__ __forceinline__ double r_one_minus_t<double>(double o) { return 1.0 - o; }
+template <>
+__device__ __forceinline__ dd r_one_minus_t<dd>(double o) {
+  dd z;
+  prec::two_sum(1.0, -o, z.hi, z.lo);
+  return z;
+}
+template <>
+__device__ __forceinline__ qd r_one_minus_t<qd>(double o) {
+  double s, e;
+  prec::two_sum(1.0, -o, s, e);
+  return qd{{s, e, 0.0, 0.0}};
+}
+
+// --------------------------------------------------------------------------
+// Complex helpers
+// --------------------------------------------------------------------------
+
+template <class R>
+__device__ __forceinline__ cx<R> c_of(double re, double im) {
+  return cx<R>{r_of<R>(re), r_of<R>(im)};
+}
+
+template <class R>
+__device__ __forceinline__ cx<R> c_conj(cx<R> a) {
+  return cx<R>{a.re, r_neg(a.im)};
+}
+
+// c - a*b
+template <class R>
+__device__ __forceinline__ cx<R> c_fms(cx<R> c, cx<R> a, cx<R> b) {
+  cx<R> z;
+  z.re = r_fma(r_fms(c.re, a.re, b.re), a.im, b.im);
+  z.im = r_fms(r_fms(c.im, a.re, b.im), a.im, b.re);
+  return z;
+}
+
+template <class R>
+__device__ __forceinline__ cx<R> c_scale(cx<R> a, R s) {
+  return cx<R>{r_mul(a.re, s), r_mul(a.im, s)};
+}
+
+// |a|^2
+template <class R>
+__device__ __forceinline__ R c_abs2(cx<R> a) {
+  return r_fma(r_mul(a.re, a.re), a.im, a.im);
+}
+
+// conj(a) * b
+template <class R>
+__device__ __forceinline__ cx<R> c_conj_mul(cx<R> a, cx<R> b) {
+  cx<R> z;
+  z.re = r_fma(r_mul(a.re, b.re), a.im, b.im);
+  z.im = r_fms(r_mul(a.re, b.im), a.im, b.re);
+  return z;
+}
+
+// --------------------------------------------------------------------------
+// Cross-lane moves (wave64)
+// --------------------------------------------------------------------------
+
+__device__ __forceinline__ double lane_bcast(double x, int lane) {
+  // lane must be wave-uniform
+  int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ dd lane_bcast(dd x, int lane) {
+  return dd{lane_bcast(x.hi, lane), lane_bcast(x.lo, lane)};
+}
+__device__ __forceinline__ qd lane_bcast(qd x, int lane) {
+  return qd{{lane_bcast(x.x[0], lane), lane_bcast(x.x[1], lane), lane_bcast(x.x[2], lane),
+             lane_bcast(x.x[3], lane)}};
+}
+template <class R>
+__device__ __forceinline__ cx<R> lane_bcast(cx<R> x, int lane) {
+  return cx<R>{lane_bcast(x.re, lane), lane_bcast(x.im, lane)};
+}
+
+__device__ __forceinline__ double lane_xor(double x, int m) { return __shfl_xor(x, m, 64); }
+__device__ __forceinline__ dd lane_xor(dd x, int m) { return dd{lane_xor(x.hi, m), lane_xor(x.lo, m)}; }
+__device__ __forceinline__ qd lane_xor(qd x, int m) {
+  return qd{{lane_xor(x.x[0], m), lane_xor(x.x[1], m), lane_xor(x.x[2], m), lane_xor(x.x[3], m)}};
+}
+
+// Sum over the 64 lanes in a fixed butterfly order; every lane gets the sum.
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v = r_add(v, lane_xor(v, m));
+  return v;
+}
+
+// --------------------------------------------------------------------------
+// Tier descriptors
+// --------------------------------------------------------------------------
+
+struct TierF64 {
+  using R = double;
+  using Acc = dd;
+  static constexpr int id = 0;
+  __device__ static Acc acc_zero() { return dd{0.0, 0.0}; }
+  __device__ static Acc acc_add(Acc a, R t) { return prec::dd_add_d(a, t); }
+  __device__ static Acc acc_merge(Acc a, Acc b) { return prec::dd_add(a, b); }
+};
+
+struct TierDD {
+  using R = dd;
+  using Acc = dd;
+  static constexpr int id = 1;
+  __device__ static Acc acc_zero() { return dd{0.0, 0.0}; }
+  __device__ static Acc acc_add(Acc a, R t) { return prec::dd_add(a, t); }
+  __device__ static Acc acc_merge(Acc a, Acc b) { return prec::dd_add(a, b); }
+};
+
+struct TierQD {
+  using R = qd;
+  using Acc = qd;
+  static constexpr int id = 2;
+  __device__ static Acc acc_zero() { return qd{{0.0, 0.0, 0.0, 0.0}}; }
+  __device__ static Acc acc_add(Acc a, R t) { return prec::qd_add(a, t); }
+  __device__ static Acc acc_merge(Acc a, Acc b) { return prec::qd_add(a, b); }
+};
+
+// |x| of a value whose sign is carried by its leading component
+__device__ __forceinline__ double r_abs(double a) { return fabs(a); }
+__device__ __forceinline__ dd r_abs(dd a) { return a.hi < 0.0 ? prec::dd_neg(a) : a; }
+__device__ __forceinline__ qd r_abs(qd a) { return a.x[0] < 0.0 ? prec::qd_neg(a) : a; }
+
+}  // namespace tor

@@ -1,0 +1,57 @@
+// tor_internal.hpp -- declarations shared by the C-ABI layer (tor_abi.cpp)
+// and the kernel launchers (tor_border.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tor.h"
+
+namespace tor {
+
+// Kernel modes of the subset-tree kernels.
+enum KernelMode : int {
+  MODE_SUM = 0,     // signed sum and |sum| per work item
+  MODE_LEVELS = 1,  // ... plus per-level sums of |term|
+  MODE_MASKS = 2,   // one explicit subset per item: its own term
+};
+
+// Per-item accumulator size in bytes for a tier (DD for F64/DD, QD for QD).
+size_t acc_bytes(int tier);
+
+// Stage O (block order, lower triangle read, leading dimension ld in complex
+// elements) into Oi: 2n x 2n, row-major, interleaved mode order
+// (row 2a+u <-> block row a + u n), both triangles filled.
+hipError_t launch_stage(const double2* O, int n, int64_t ld, double2* Oi, hipStream_t s);
+
+// Zero `count` 32-bit words (a kernel, so the call is safe inside a captured graph).
+hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t s);
+
+// Bordered-Cholesky subset-tree kernel.  items: prefix masks (MODE_SUM /
+// MODE_LEVELS, over modes [0, d)) or full subsets (MODE_MASKS).  partials:
+// [nitems][ncols] accumulators, ncols = 2 (+ n+1 for MODE_LEVELS).
+struct BorderLaunch {
+  int tier, mode, n, d, nitems, grid;
+  const double2* Oi;
+  const uint64_t* items;
+  uint32_t* queue;
+  void* partials;
+  int32_t* status;
+};
+size_t border_lds_bytes(int tier, int mode, int n);
+hipError_t border_occupancy(int tier, int mode, int n, int* blocks_per_cu);
+hipError_t launch_border(const BorderLaunch& a, hipStream_t s);
+
+// Fixed-order reduction of partials [nitems][ncols] into red [ncols].
+hipError_t launch_reduce_cols(int tier, const void* partials, int nitems, int ncols, void* red,
+                              hipStream_t s);
+
+// Build the tor_result_t from the two reduced columns (signed sum, |sum|).
+hipError_t launch_finalize(int tier, const void* red, const int32_t* status, double err_rel,
+                           tor_result_t* out, hipStream_t s);
+
+// Copy column 0 of partials [nitems][2] into out4 (4 doubles per item).
+hipError_t launch_expand_terms(int tier, const void* partials, int nitems, double* out4,
+                               hipStream_t s);
+
+}  // namespace tor

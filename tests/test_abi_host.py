@@ -1,0 +1,85 @@
+"""The C-ABI library loads, exports what include/tor.h declares, and its
+host-side logic (Alg. 2 mask functions, work-item plan, argument checks)
+behaves; nothing here needs a GPU."""
+import ctypes
+import itertools
+import os
+import re
+from math import comb
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2009_01177_amd import _lib
+    return _lib.lib()
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "tor.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tor_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    syms = declared_symbols()
+    assert "tor_eval" in syms and "tor_debug_sampled_terms" in syms
+    from paper_2009_01177_amd import _lib
+    assert sorted(_lib.EXPORTS) == syms
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+def test_next_mask_worked_example(L):
+    # Sec. 4.1: "010011" -> "001110"
+    assert L.tor_next_mask(0b010011) == 0b001110
+
+
+@pytest.mark.parametrize("N,c", [(6, 2), (7, 3), (10, 5), (12, 1), (9, 9), (8, 0)])
+def test_mask_enumeration_brute_force(L, N, c):
+    want = sorted((sum(1 << (N - 1 - j) for j in pos) for pos in itertools.combinations(range(N), c)),
+                  reverse=True)
+    got = [L.tor_kth_mask(N, c, k) for k in range(comb(N, c))]
+    assert got == want
+    m = L.tor_kth_mask(N, c, 0)
+    seq = []
+    for _ in range(comb(N, c)):
+        seq.append(m)
+        m = L.tor_next_mask(m)
+    if c > 0:
+        assert seq == want
+        assert m == 0  # sentinel after the last mask
+
+
+def test_kth_mask_out_of_range(L):
+    assert L.tor_kth_mask(6, 2, comb(6, 2)) == 0
+    assert L.tor_kth_mask(6, 7, 0) == 0
+
+
+@pytest.mark.parametrize("n,d", [(5, 3), (12, 12), (20, 10), (30, 0)])
+def test_plan_covers_every_prefix_once_largest_first(n, d):
+    from paper_2009_01177_amd import tor_plan_items
+    items = tor_plan_items(n, d)
+    assert sorted(items.tolist()) == list(range(1 << d))
+    pops = [bin(int(x)).count("1") for x in items]
+    assert pops == sorted(pops, reverse=True)
+
+
+def test_argument_checks_need_no_gpu(L):
+    from paper_2009_01177_amd import _lib
+    out = _lib.TorResultC()
+    dummy = ctypes.c_void_p(16)
+    assert L.tor_eval(dummy, -1, 2, 1, None, None, ctypes.byref(out)) == _lib.TOR_EINVAL
+    assert L.tor_eval(dummy, _lib.TOR_NMAX + 1, 200, 1, None, None, ctypes.byref(out)) == _lib.TOR_EINVAL
+    assert L.tor_eval(dummy, 3, 6, 7, None, None, ctypes.byref(out)) == _lib.TOR_EINVAL
+    assert L.tor_eval(dummy, 3, 5, 1, None, None, ctypes.byref(out)) == _lib.TOR_EINVAL  # ld < 2n
+    assert L.tor_eval(None, 3, 6, 1, None, None, ctypes.byref(out)) == _lib.TOR_EINVAL
+    assert L.tor_eval(dummy, 3, 6, 1, None, None, None) == _lib.TOR_EINVAL
+    # n = 0 is the empty product and needs no device
+    assert L.tor_eval(None, 0, 0, 1, None, None, ctypes.byref(out)) == 0
+    assert out.tor[0] == 1.0 and out.abs_sum[0] == 1.0
+    assert L.tor_strerror(_lib.TOR_ENOTPD).decode().startswith("I - O")
