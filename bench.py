@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark: Torontonian subset-terms/s at n = 30 on one MI355X.
+
+A step is one full evaluation Tor(O) of the n = 30 workload (100-mode lossy
+GBS state, Haar unitary, r ~ U[0.8, 1.6], transmission 0.3, 30 clicked modes;
+synthetic, seeded) with O already resident in HBM: staging, the subset-tree
+kernel over all 2^30 subsets, the fixed-order reduction and the copy of the
+result to the host.  The timed tier is double-double (the paper's 128-bit
+tier); the FP64 tier is measured on the same input and reported beside it.
+
+Prints one JSON line.  `value` = 2^30 / seconds per step.  `roofline` is for
+the subset-tree kernel: algorithmic FP64 flops per launch (complex
+multiply-adds of the bordered update, per subset of size m with parent size
+t = m - 1: 4 t^2 + 6 t, times the FP64 operations one complex multiply-add
+costs in the tier) over that kernel's duration, measured by HIP events on the
+stream it runs on, against the 78.6 TFLOP/s FP64 vector peak.
+`cpu_baseline` is the float128 oracle timed on the host's cores over a
+bounded random sample of the same workload's subsets.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
+# FP64 operations per complex multiply-add in each tier's arithmetic:
+#   FP64: 4 fused multiply-adds = 8 flops;
+#   DD  : 4 double-double products (12 flops each, FMA form) and
+#         4 accurate double-double additions (20 flops each) = 128 flops.
+FLOPS_PER_CFMA = {"fp64": 8, "dd": 128}
+
+
+def cfma_bordered(n: int) -> int:
+    """Complex multiply-adds of the bordered update over all non-empty subsets."""
+    tot = 0
+    for m in range(1, n + 1):
+        t = m - 1
+        tot += math.comb(n, m) * (4 * t * t + 6 * t)
+    return tot
+
+
+def paper_eq9_flops(n: int) -> float:
+    """Eq. 9: the paper's count for per-subset elimination."""
+    return sum(math.comb(n, i) * (32.0 / 3 * i ** 3 + 4 * i * i - 8.0 / 3 * i) for i in range(1, n + 1))
+
+
+def time_tier(tor, Od, tier, steps, warmup, algo="auto", split=-1):
+    import torch
+    for _ in range(warmup):
+        tor.tor_eval(Od, tier=tier, algo=algo, split_depth=split, time_kernel=True)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    kms = []
+    res = None
+    t0.record()
+    for _ in range(steps):
+        res = tor.tor_eval(Od, tier=tier, algo=algo, split_depth=split, time_kernel=True)
+        kms.append(tor.tor_last_kernel_ms())
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    return ms, kms, res
+
+
+def cpu_baseline(O, n, seconds: float):
+    """float128 oracle terms/s on a bounded uniform sample of subsets."""
+    import numpy as np
+    import oracle
+    threads = oracle.max_threads()
+    rng = np.random.default_rng(12345)
+    k = 64
+    while True:
+        masks = rng.integers(0, 1 << n, size=k, dtype=np.uint64)
+        t = time.perf_counter()
+        oracle.terms(O, masks, threads=threads)
+        dt = time.perf_counter() - t
+        if dt > seconds / 4 or k >= 1 << 22:
+            break
+        k = int(k * min(16.0, max(2.0, (seconds / 4) / max(dt, 1e-3))))
+    # final timed sample of about `seconds`
+    k2 = max(k, int(k * seconds / max(dt, 1e-6)))
+    masks = rng.integers(0, 1 << n, size=k2, dtype=np.uint64)
+    t = time.perf_counter()
+    oracle.terms(O, masks, threads=threads)
+    dt = time.perf_counter() - t
+    return dict(value=k2 / dt, unit="terms/s", cores=threads, kind="oracle",
+                sample=f"{k2} uniformly random subsets of the n={n} workload, "
+                       f"binary128 per-subset Cholesky, {dt:.1f} s on {threads} threads")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=30)
+    ap.add_argument("--tier", default="dd", choices=["dd", "fp64"])
+    ap.add_argument("--algo", default="auto")
+    ap.add_argument("--split", type=int, default=-1)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build evaluates a Torontonian on a single "
+              "MI355X (--gpus 1); multi-GPU sharding of the subset tree is not implemented.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import gbs_inputs as g
+    import paper_2009_01177_amd as tor
+
+    n = args.n
+    O, modes = g.workload("n30_lossy", n=n)
+    Od = torch.from_numpy(O).to("cuda:0")
+    torch.cuda.synchronize()
+    print(f"[bench] n={n} tier={args.tier} steps={args.steps} warmup={args.warmup}", file=sys.stderr,
+          flush=True)
+
+    ms, kms, res = time_tier(tor, Od, args.tier, args.steps, args.warmup, args.algo, args.split)
+    terms = float(1 << n)
+    value = terms / (ms / 1e3)
+    kernel_ms = float(np.mean([k[0] for k in kms]))
+    d_used, grid_used = kms[-1][1], kms[-1][2]
+    flops = cfma_bordered(n) * FLOPS_PER_CFMA[args.tier]
+    achieved = flops / (kernel_ms / 1e3) / 1e12
+    print(f"[bench] {args.tier}: {ms:.1f} ms/step, kernel {kernel_ms:.1f} ms, {value:.3e} terms/s, "
+          f"{achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
+
+    other = "fp64" if args.tier == "dd" else "dd"
+    oms, okms, ores = time_tier(tor, Od, other, args.fp64_steps, 1, args.algo, args.split)
+    okernel = float(np.mean([k[0] for k in okms]))
+    oflops = cfma_bordered(n) * FLOPS_PER_CFMA[other]
+    print(f"[bench] {other}: {oms:.1f} ms/step, kernel {okernel:.1f} ms", file=sys.stderr, flush=True)
+
+    line = {
+        "metric": f"Torontonian subset-terms/s at n={n} ({args.tier.upper()} tier)",
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64x2" if args.tier == "dd" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"single Torontonian n={n}: 100-mode lossy GBS (Haar U, r~U[0.8,1.6], "
+                               f"eta=0.3), {n} clicked modes, O {2 * n}x{2 * n} complex128",
+                   "n": n, "terms": int(terms), "tier": args.tier, "split_depth": d_used,
+                   "grid": grid_used},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "border_kernel", "kernel_ms": kernel_ms,
+                     "algorithmic_flops": flops},
+        "tiers": {
+            args.tier: {"terms_per_s": value, "ms_per_step": ms, "kernel_ms": kernel_ms,
+                        "tflops": achieved, "frac_fp64_peak": achieved / PEAK_FP64_TFLOPS,
+                        "tor": res.value, "kappa": res.kappa},
+            other: {"terms_per_s": terms / (oms / 1e3), "ms_per_step": oms, "kernel_ms": okernel,
+                    "tflops": oflops / (okernel / 1e3) / 1e12,
+                    "frac_fp64_peak": oflops / (okernel / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+                    "tor": ores.value},
+        },
+        "paper_eq9_equivalent_pflops": paper_eq9_flops(n) / (ms / 1e3) / 1e15,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(O, n, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -87,8 +87,12 @@ typedef struct tor_options {
   int32_t split_depth; /* d: number of leading modes whose subsets form the
                           work items (2^d of them); -1 = autotuned */
   int32_t grid;        /* persistent workgroups; 0 = from occupancy */
-  int32_t reserved;
+  int32_t flags;       /* TOR_FLAG_* bits */
 } tor_options_t;
+
+/* Record HIP events around the subset-tree kernel (on the caller's stream);
+ * read the duration back with tor_last_kernel_ms(). */
+#define TOR_FLAG_TIME_KERNEL 1
 
 /* Library version string. */
 const char* tor_version(void);
@@ -130,6 +134,12 @@ int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, voi
  * Enqueued on `stream`; returns without waiting. */
 int tor_debug_sampled_terms(const void* O, int32_t n, int64_t ld, int32_t tier,
                             const uint64_t* masks, int64_t k, void* stream, double* out_terms);
+
+/* Duration in milliseconds of the subset-tree kernel of the last synchronous
+ * evaluation on the current device that set TOR_FLAG_TIME_KERNEL (HIP
+ * events recorded on the caller's stream around that one launch), and the
+ * split depth and grid it ran with; -1 if none. */
+double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid);
 
 /* ---- Host-side scheduling helpers (no GPU needed) ----------------------
  * Alg. 2's mask functions, used to order the work items by subset size. */

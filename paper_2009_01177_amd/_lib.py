@@ -16,11 +16,12 @@ TOR_OK, TOR_EINVAL, TOR_ENOTPD, TOR_EHIP, TOR_ENOMEM, TOR_EUNSUPPORTED = 0, -1, 
 TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO = 0, 1, 2, -1
 TOR_ALGO_AUTO, TOR_ALGO_BORDER = 0, 1
 TOR_NMAX = 48
+TOR_FLAG_TIME_KERNEL = 1
 
 # Every symbol include/tor.h declares.
 EXPORTS = (
     "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval",
-    "tor_debug_level_sums", "tor_debug_sampled_terms",
+    "tor_debug_level_sums", "tor_debug_sampled_terms", "tor_last_kernel_ms",
     "tor_next_mask", "tor_kth_mask", "tor_plan_items",
 )
 
@@ -40,7 +41,7 @@ class TorOptionsC(ctypes.Structure):
         ("algo", ctypes.c_int32),
         ("split_depth", ctypes.c_int32),
         ("grid", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
     ]
 
 
@@ -85,6 +86,8 @@ def lib():
     L.tor_debug_level_sums.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
     L.tor_debug_sampled_terms.restype = ctypes.c_int
     L.tor_debug_sampled_terms.argtypes = [vp, i32, i64, i32, vp, i64, vp, vp]
+    L.tor_last_kernel_ms.restype = ctypes.c_double
+    L.tor_last_kernel_ms.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.tor_next_mask.restype = u64
     L.tor_next_mask.argtypes = [u64]
     L.tor_kth_mask.restype = u64

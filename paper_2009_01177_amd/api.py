@@ -104,10 +104,11 @@ def tor_shutdown():
 
 
 def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
-             stream=None, raise_on_error: bool = True) -> TorResult:
+             stream=None, raise_on_error: bool = True, time_kernel: bool = False) -> TorResult:
     """Tor(O) of one instance (synchronous)."""
     Od, n, ld = _device_o(O)
-    opt = _lib.TorOptionsC(algo_id(algo), int(split_depth), int(grid), 0)
+    flags = _lib.TOR_FLAG_TIME_KERNEL if time_kernel else 0
+    opt = _lib.TorOptionsC(algo_id(algo), int(split_depth), int(grid), flags)
     out = _lib.TorResultC()
     rc = lib().tor_eval(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), ctypes.byref(opt),
                         _stream_ptr(stream), ctypes.byref(out))
@@ -145,6 +146,14 @@ def tor_debug_sampled_terms(O, masks, tier="dd", stream=None) -> np.ndarray:
     check(rc, "tor_debug_sampled_terms")
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
     return out.cpu().numpy()
+
+
+def tor_last_kernel_ms():
+    """(ms, split_depth, grid) of the last timed subset-tree kernel."""
+    d = ctypes.c_int32(-1)
+    gr = ctypes.c_int32(-1)
+    ms = lib().tor_last_kernel_ms(ctypes.byref(d), ctypes.byref(gr))
+    return float(ms), int(d.value), int(gr.value)
 
 
 # ---- host scheduling helpers (no GPU) -------------------------------------

@@ -32,6 +32,10 @@ struct Workspace {
   tor_result_t* host_res = nullptr;  // pinned
   double* host_lev = nullptr;        // pinned, 4*(TOR_NMAX+1)
   std::map<std::pair<int, int>, ItemTable> tables;  // (n, d) -> prefix items
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // kernel timing (TOR_FLAG_TIME_KERNEL)
+  bool timed = false;                        // events of the last launch are valid
+  double last_ms = -1.0;
+  int last_d = -1, last_grid = -1;
 };
 
 std::mutex g_mu;
@@ -213,7 +217,17 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
   bl.queue = cnt;
   bl.partials = w->buf + o_part;
   bl.status = (int32_t*)(cnt + 1);
+  const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
+  if (timed) {
+    if (!w->ev0) TOR_HIP(hipEventCreate(&w->ev0));
+    if (!w->ev1) TOR_HIP(hipEventCreate(&w->ev1));
+    TOR_HIP(hipEventRecord(w->ev0, s));
+  }
   TOR_HIP(launch_border(bl, s));
+  if (timed) TOR_HIP(hipEventRecord(w->ev1, s));
+  w->timed = timed;
+  w->last_d = d;
+  w->last_grid = grid;
   TOR_HIP(launch_reduce_cols(tier, w->buf + o_part, nitems, ncols, w->buf + o_red, s));
   const double err_rel = (double)(4 * n * n + d + 8) * unit_roundoff(tier);
   TOR_HIP(launch_finalize(tier, w->buf + o_red, (const int32_t*)(cnt + 1), err_rel,
@@ -262,6 +276,8 @@ int tor_shutdown(void) {
       if (w->buf) (void)hipFree(w->buf);
       if (w->host_res) (void)hipHostFree(w->host_res);
       if (w->host_lev) (void)hipHostFree(w->host_lev);
+      if (w->ev0) (void)hipEventDestroy(w->ev0);
+      if (w->ev1) (void)hipEventDestroy(w->ev1);
       (void)hipSetDevice(cur);
     }
     delete w;
@@ -285,8 +301,21 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
   TOR_TRY(enqueue_tree(w, O, n, ld, tier, MODE_SUM, opt, s, &ro));
   TOR_HIP(hipMemcpyAsync(w->host_res, ro.dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
   TOR_HIP(hipStreamSynchronize(s));
+  if (w->timed) {
+    float ms = -1.0f;
+    TOR_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
+    w->last_ms = ms;
+  }
   *out = *w->host_res;
   return out->status;
+}
+
+double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid) {
+  Workspace* w = nullptr;
+  if (get_ws(&w) != TOR_OK) return -1.0;
+  if (split_depth) *split_depth = w->last_d;
+  if (grid) *grid = w->last_grid;
+  return w->last_ms;
 }
 
 int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
