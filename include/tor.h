@@ -64,9 +64,13 @@ typedef enum {
  * along each path. */
 typedef enum {
   TOR_ALGO_AUTO = 0,
-  TOR_ALGO_BORDER = 1 /* bordered Cholesky: appending a mode adds two rows to
-                         the factor, O(|Z|^2) per subset (Sec. 4.2's
-                         elimination made incremental) */
+  TOR_ALGO_BORDER = 1, /* bordered Cholesky: appending a mode adds two rows to
+                          the factor, O(|Z|^2) per subset (Sec. 4.2's
+                          elimination made incremental) */
+  TOR_ALGO_SCHUR = 2   /* right-looking: each state carries the Schur
+                          complement of the undecided modes, in the real
+                          quadrature basis; taking a mode in is a rank-2
+                          update, about 12 of them per subset amortised */
 } tor_algo_t;
 
 /* Result of one Torontonian. 64 bytes. */

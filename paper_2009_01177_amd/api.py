@@ -13,7 +13,7 @@ from . import _lib
 from ._lib import TorError, check, lib
 
 _TIERS = {"fp64": _lib.TOR_FP64, "dd": _lib.TOR_DD, "qd": _lib.TOR_QD, "auto": _lib.TOR_AUTO}
-_ALGOS = {"auto": _lib.TOR_ALGO_AUTO, "border": _lib.TOR_ALGO_BORDER}
+_ALGOS = {"auto": _lib.TOR_ALGO_AUTO, "border": _lib.TOR_ALGO_BORDER, "schur": _lib.TOR_ALGO_SCHUR}
 
 
 def tier_id(tier) -> int:

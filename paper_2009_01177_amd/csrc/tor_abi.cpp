@@ -6,6 +6,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -176,7 +177,6 @@ struct RunOut {
 // reduction, finalize.  Device result in *ro.
 int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int mode,
                  const tor_options_t* opt, hipStream_t s, RunOut* ro) {
-  if (opt && opt->algo != TOR_ALGO_AUTO && opt->algo != TOR_ALGO_BORDER) return TOR_EINVAL;
   TOR_TRY(fits_border(w, tier, mode, n));
   int occ = 0;
   TOR_HIP(border_occupancy(tier, mode, n, &occ));
@@ -235,6 +235,115 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
   ro->dres = (tor_result_t*)(w->buf + o_res);
   ro->red = w->buf + o_red;
   ro->ncols = ncols;
+  return TOR_OK;
+}
+
+
+// Right-looking Schur-complement evaluation (MODE_SUM only).
+//   depth 0 -> D_c : breadth-first in HBM, all states kept ("roots")
+//   per root       : breadth-first D_c -> D_m = n - s_m, then the middle +
+//                    bottom kernel over the 2^(D_m - D_c) middle states
+// D_c is chosen so that one root's expansion has at most 2^17 middle states.
+int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
+                  const tor_options_t* opt, hipStream_t s, RunOut* ro) {
+  int s_m = 0, s_b = 0;
+  schur_levels(tier, n, &s_m, &s_b);
+  const int D_m = n - s_m;
+  const int LT = 17;
+  const int D_c = D_m > LT ? D_m - LT : 0;
+  const int Dl = D_m - D_c;  // levels expanded per root
+  const int nchunks = 1 << D_c;
+  const size_t rb = schur_value_bytes(tier);
+  const size_t ab = acc_bytes(tier);
+  auto ps = [](int k) { return (size_t)k * (2 * k + 1); };
+
+  // largest level of the stage-0 and per-root expansions
+  size_t lvl_vals = ps(n);
+  for (int j = 1; j <= D_c; ++j) lvl_vals = std::max(lvl_vals, ((size_t)1 << j) * ps(n - j));
+  for (int j = 1; j <= Dl; ++j) lvl_vals = std::max(lvl_vals, ((size_t)1 << j) * ps(n - D_c - j));
+  const size_t lvl_states = (size_t)1 << std::max(D_c, Dl);
+  const size_t mids = (size_t)1 << Dl;
+
+  Carver c;
+  const size_t o_rm = c.take(rb * ((size_t)nchunks * ps(n - D_c)));
+  const size_t o_rg = c.take(rb * nchunks);
+  const size_t o_rn = c.take(sizeof(int32_t) * nchunks);
+  size_t o_m[2], o_g[2], o_n[2];
+  for (int k = 0; k < 2; ++k) {
+    o_m[k] = c.take(rb * lvl_vals);
+    o_g[k] = c.take(rb * lvl_states);
+    o_n[k] = c.take(sizeof(int32_t) * lvl_states);
+  }
+  const size_t o_part = c.take(ab * 2 * mids);
+  const size_t o_chunk = c.take(ab * 2 * (size_t)nchunks);
+  const size_t o_red = c.take(ab * 2);
+  const size_t o_cnt = c.take(sizeof(uint32_t) * 64);
+  const size_t o_res = c.take(sizeof(tor_result_t));
+  TOR_TRY(ensure_cap(w, c.off));
+  char* B = w->buf;
+  uint32_t* cnt = (uint32_t*)(B + o_cnt);
+  int32_t* status = (int32_t*)(cnt + 1);
+
+  int occ = 0;
+  TOR_HIP(leaf_occupancy(tier, s_b, &occ));
+  if (occ < 1) return TOR_EUNSUPPORTED;
+  int grid = (opt && opt->grid > 0) ? opt->grid : occ * w->cus;
+  if ((size_t)grid > mids) grid = (int)mids;
+
+  TOR_HIP(launch_zero_words(cnt, 64, s));
+  const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
+  if (timed) {
+    if (!w->ev0) TOR_HIP(hipEventCreate(&w->ev0));
+    if (!w->ev1) TOR_HIP(hipEventCreate(&w->ev1));
+    TOR_HIP(hipEventRecord(w->ev0, s));
+  }
+  // stage 0: root, then breadth-first to depth D_c into the roots buffer
+  {
+    int cur = 0;
+    void* dm = D_c == 0 ? (void*)(B + o_rm) : (void*)(B + o_m[0]);
+    void* dg = D_c == 0 ? (void*)(B + o_rg) : (void*)(B + o_g[0]);
+    int32_t* dn = D_c == 0 ? (int32_t*)(B + o_rn) : (int32_t*)(B + o_n[0]);
+    TOR_HIP(launch_real_root(tier, (const double2*)O, n, ld, dm, dg, dn, s));
+    for (int j = 0; j < D_c; ++j) {
+      const bool last = (j == D_c - 1);
+      void* om = last ? (void*)(B + o_rm) : (void*)(B + o_m[1 - cur]);
+      void* og = last ? (void*)(B + o_rg) : (void*)(B + o_g[1 - cur]);
+      int32_t* on = last ? (int32_t*)(B + o_rn) : (int32_t*)(B + o_n[1 - cur]);
+      TOR_HIP(launch_expand(tier, B + o_m[cur], B + o_g[cur], (const int32_t*)(B + o_n[cur]), n - j,
+                            1 << j, om, og, on, status, s));
+      cur = 1 - cur;
+    }
+  }
+  // per root: expand Dl levels, then the middle + bottom kernel
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const char* im = B + o_rm + rb * ((size_t)ch * ps(n - D_c));
+    const char* ig = B + o_rg + rb * ch;
+    const int32_t* in_ = (const int32_t*)(B + o_rn) + ch;
+    int cur = -1;  // -1: the root itself
+    for (int j = 0; j < Dl; ++j) {
+      const int nx = (cur == 0) ? 1 : 0;
+      TOR_HIP(launch_expand(tier, cur < 0 ? (const void*)im : (const void*)(B + o_m[cur]),
+                            cur < 0 ? (const void*)ig : (const void*)(B + o_g[cur]),
+                            cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]), n - D_c - j, 1 << j,
+                            B + o_m[nx], B + o_g[nx], (int32_t*)(B + o_n[nx]), status, s));
+      cur = nx;
+    }
+    const void* lm = cur < 0 ? (const void*)im : (const void*)(B + o_m[cur]);
+    const void* lg = cur < 0 ? (const void*)ig : (const void*)(B + o_g[cur]);
+    const int32_t* ln = cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]);
+    TOR_HIP(launch_leaf(tier, s_m, s_b, lm, lg, ln, (int)mids, n, B + o_part, status, grid, s));
+    TOR_HIP(launch_reduce_cols(tier, B + o_part, (int)mids, 2, B + o_chunk + ab * 2 * ch, s));
+  }
+  if (timed) TOR_HIP(hipEventRecord(w->ev1, s));
+  w->timed = timed;
+  w->last_d = D_m;
+  w->last_grid = grid;
+  TOR_HIP(launch_reduce_cols(tier, B + o_chunk, nchunks, 2, B + o_red, s));
+  const double err_rel = (double)(4 * n * n + n + 8) * unit_roundoff(tier);
+  TOR_HIP(launch_finalize(tier, B + o_red, status, err_rel, (tor_result_t*)(B + o_res), s));
+  ro->dres = (tor_result_t*)(B + o_res);
+  ro->red = B + o_red;
+  ro->ncols = 2;
   return TOR_OK;
 }
 
@@ -298,7 +407,12 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
   RunOut ro;
-  TOR_TRY(enqueue_tree(w, O, n, ld, tier, MODE_SUM, opt, s, &ro));
+  const int algo = opt ? opt->algo : TOR_ALGO_AUTO;
+  if (algo != TOR_ALGO_AUTO && algo != TOR_ALGO_BORDER && algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
+  if (algo == TOR_ALGO_BORDER)
+    TOR_TRY(enqueue_tree(w, O, n, ld, tier, MODE_SUM, opt, s, &ro));
+  else
+    TOR_TRY(enqueue_schur(w, O, n, ld, tier, opt, s, &ro));
   TOR_HIP(hipMemcpyAsync(w->host_res, ro.dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
   TOR_HIP(hipStreamSynchronize(s));
   if (w->timed) {

@@ -54,4 +54,17 @@ hipError_t launch_finalize(int tier, const void* red, const int32_t* status, dou
 hipError_t launch_expand_terms(int tier, const void* partials, int nitems, double* out4,
                                hipStream_t s);
 
+// ---- right-looking Schur-complement kernels (tor_schur.hip) ----
+size_t schur_value_bytes(int tier);
+// middle-level (s_m) and bottom-level (s_b) mode counts for a tier and n
+void schur_levels(int tier, int n, int* s_m, int* s_b);
+hipError_t launch_real_root(int tier, const double2* O, int n, int64_t ld, void* mat, void* g,
+                            int32_t* m, hipStream_t s);
+hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
+                         int s, int nst, void* out_mat, void* out_g, int32_t* out_m,
+                         int32_t* status, hipStream_t st);
+hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
+                       int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st);
+hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu);
+
 }  // namespace tor
