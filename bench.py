@@ -3,17 +3,26 @@
 
 A step is one full evaluation Tor(O) of the n = 30 workload (100-mode lossy
 GBS state, Haar unitary, r ~ U[0.8, 1.6], transmission 0.3, 30 clicked modes;
-synthetic, seeded) with O already resident in HBM: staging, the subset-tree
-kernel over all 2^30 subsets, the fixed-order reduction and the copy of the
+synthetic, seeded) with O already resident in HBM: staging, every subset-tree
+kernel over all 2^30 subsets, the fixed-order reductions and the copy of the
 result to the host.  The timed tier is double-double (the paper's 128-bit
 tier); the FP64 tier is measured on the same input and reported beside it.
 
 Prints one JSON line.  `value` = 2^30 / seconds per step.  `roofline` is for
-the subset-tree kernel: algorithmic FP64 flops per launch (complex
-multiply-adds of the bordered update, per subset of size m with parent size
-t = m - 1: 4 t^2 + 6 t, times the FP64 operations one complex multiply-add
-costs in the tier) over that kernel's duration, measured by HIP events on the
-stream it runs on, against the 78.6 TFLOP/s FP64 vector peak.
+the dominant kernel (the middle+bottom kernel of the Schur path, or the
+bordered kernel): algorithmic FP64 operations per launch over that kernel's
+average launch duration, measured by HIP events the library records on the
+stream it launches on, against the 78.6 TFLOP/s FP64 vector peak.  The
+operation counts are those of the arithmetic the method performs (one count
+per FP64 add, multiply, square root or division; a fused multiply-add counts
+two), per subset, in each tier:
+  Schur path, a subset whose largest mode leaves s undecided modes:
+      s(2s+1) updated entries (two multiply-subtracts each), 2s scaled
+      pivot-column entries, one 2x2 pivot (two reciprocal square roots) and
+      the running det^(-1/2) product; plus two compensated accumulations of
+      every term.
+  Bordered path, a subset of m modes: 4(m-1)^2 + 6(m-1) complex
+      multiply-adds.
 `cpu_baseline` is the float128 oracle timed on the host's cores over a
 bounded random sample of the same workload's subsets.
 """
@@ -36,6 +45,37 @@ PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/C
 #   DD  : 4 double-double products (12 flops each, FMA form) and
 #         4 accurate double-double additions (20 flops each) = 128 flops.
 FLOPS_PER_CFMA = {"fp64": 8, "dd": 128}
+
+
+def kernel_flops(n, tier, algo, dmid):
+    """Algorithmic flops of the dominant kernel over one evaluation."""
+    if algo == "border":
+        return cfma_bordered(n) * FLOPS_PER_CFMA[tier]
+    return schur_flops(n, tier, dmid) + (1 << n) * acc_flops(tier)
+
+
+def schur_node_flops(sp: int, tier: str) -> int:
+    """One include producing a child with sp undecided modes."""
+    ent, rows = sp * (2 * sp + 1), 2 * sp
+    if tier == "fp64":
+        # entry: 2 FMA; row: mul, FMA, mul; pivot: 2 x (sqrt, div), mul, FMA, 2 mul
+        return 4 * ent + 4 * rows + 9
+    # DD: multiply-subtract = DWTimesDW (12) + AccurateDWPlusDW (20);
+    # row: 2 DD multiplies + 1 multiply-subtract; pivot: 2 DD rsqrt (24 each),
+    # a DD multiply, a multiply-subtract, 2 DD multiplies
+    return 64 * ent + 56 * rows + 116
+
+
+def acc_flops(tier: str) -> int:
+    """Compensated accumulation of one term into the signed and magnitude sums."""
+    return 2 * 10 if tier == "fp64" else 2 * 20
+
+
+def schur_flops(n: int, tier: str, dmin: int = 0) -> int:
+    """Algorithmic flops of the includes at depth >= dmin (2^k subsets have
+    largest mode k), plus every term's accumulation when dmin covers the
+    kernel that emits them."""
+    return sum((1 << k) * schur_node_flops(n - 1 - k, tier) for k in range(dmin, n))
 
 
 def cfma_bordered(n: int) -> int:
@@ -100,13 +140,13 @@ def cpu_baseline(O, n, seconds: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=30)
     ap.add_argument("--tier", default="dd", choices=["dd", "fp64"])
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--split", type=int, default=-1)
-    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -129,21 +169,22 @@ def main():
     print(f"[bench] n={n} tier={args.tier} steps={args.steps} warmup={args.warmup}", file=sys.stderr,
           flush=True)
 
-    ms, kms, res = time_tier(tor, Od, args.tier, args.steps, args.warmup, args.algo, args.split)
+    algo = "border" if args.algo == "border" else "schur"
+    ms, kms, res = time_tier(tor, Od, args.tier, args.steps, args.warmup, algo, args.split)
     terms = float(1 << n)
     value = terms / (ms / 1e3)
-    kernel_ms = float(np.mean([k[0] for k in kms]))
-    d_used, grid_used = kms[-1][1], kms[-1][2]
-    flops = cfma_bordered(n) * FLOPS_PER_CFMA[args.tier]
+    kernel_ms = float(np.mean([k[0] for k in kms]))  # sum over the step's launches
+    d_used, grid_used, launches = kms[-1][1], kms[-1][2], kms[-1][3]
+    flops = kernel_flops(n, args.tier, algo, d_used)
     achieved = flops / (kernel_ms / 1e3) / 1e12
-    print(f"[bench] {args.tier}: {ms:.1f} ms/step, kernel {kernel_ms:.1f} ms, {value:.3e} terms/s, "
-          f"{achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
+    print(f"[bench] {args.tier}: {ms:.3f} ms/step, kernel {kernel_ms:.3f} ms over {launches} launches, "
+          f"{value:.3e} terms/s, {achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
 
     other = "fp64" if args.tier == "dd" else "dd"
-    oms, okms, ores = time_tier(tor, Od, other, args.fp64_steps, 1, args.algo, args.split)
+    oms, okms, ores = time_tier(tor, Od, other, args.fp64_steps, 1, algo, args.split)
     okernel = float(np.mean([k[0] for k in okms]))
-    oflops = cfma_bordered(n) * FLOPS_PER_CFMA[other]
-    print(f"[bench] {other}: {oms:.1f} ms/step, kernel {okernel:.1f} ms", file=sys.stderr, flush=True)
+    oflops = kernel_flops(n, other, algo, okms[-1][1])
+    print(f"[bench] {other}: {oms:.3f} ms/step, kernel {okernel:.3f} ms", file=sys.stderr, flush=True)
 
     line = {
         "metric": f"Torontonian subset-terms/s at n={n} ({args.tier.upper()} tier)",
@@ -160,12 +201,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"single Torontonian n={n}: 100-mode lossy GBS (Haar U, r~U[0.8,1.6], "
                                f"eta=0.3), {n} clicked modes, O {2 * n}x{2 * n} complex128",
-                   "n": n, "terms": int(terms), "tier": args.tier, "split_depth": d_used,
-                   "grid": grid_used},
+                   "n": n, "terms": int(terms), "tier": args.tier, "algo": algo,
+                   "split_depth": d_used, "grid": grid_used},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "border_kernel", "kernel_ms": kernel_ms,
-                     "algorithmic_flops": flops},
+                     "kernel": "leaf_kernel" if algo == "schur" else "border_kernel",
+                     "launches_per_step": launches,
+                     "kernel_ms_per_launch": kernel_ms / max(launches, 1),
+                     "algorithmic_flops_per_launch": flops / max(launches, 1)},
         "tiers": {
             args.tier: {"terms_per_s": value, "ms_per_step": ms, "kernel_ms": kernel_ms,
                         "tflops": achieved, "frac_fp64_peak": achieved / PEAK_FP64_TFLOPS,
@@ -176,6 +219,8 @@ def main():
                     "tor": ores.value},
         },
         "paper_eq9_equivalent_pflops": paper_eq9_flops(n) / (ms / 1e3) / 1e15,
+        "algorithmic_flops_all_kernels": (schur_flops(n, args.tier) + (1 << n) * acc_flops(args.tier))
+        if algo == "schur" else flops,
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

@@ -139,11 +139,14 @@ int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, voi
 int tor_debug_sampled_terms(const void* O, int32_t n, int64_t ld, int32_t tier,
                             const uint64_t* masks, int64_t k, void* stream, double* out_terms);
 
-/* Duration in milliseconds of the subset-tree kernel of the last synchronous
- * evaluation on the current device that set TOR_FLAG_TIME_KERNEL (HIP
- * events recorded on the caller's stream around that one launch), and the
- * split depth and grid it ran with; -1 if none. */
-double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid);
+/* Time of the dominant kernel in the last synchronous evaluation on the
+ * current device that set TOR_FLAG_TIME_KERNEL: the sum, in milliseconds,
+ * of HIP-event durations recorded on the caller's stream around each launch
+ * of the bordered kernel (TOR_ALGO_BORDER) or of the middle+bottom kernel
+ * (TOR_ALGO_SCHUR).  *launches receives the number of launches, *split_depth
+ * the split depth (border) or the middle-level depth n - s_m (Schur),
+ * *grid the workgroups per launch.  Any pointer may be NULL.  -1 if none. */
+double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches);
 
 /* ---- Host-side scheduling helpers (no GPU needed) ----------------------
  * Alg. 2's mask functions, used to order the work items by subset size. */

@@ -87,7 +87,7 @@ def lib():
     L.tor_debug_sampled_terms.restype = ctypes.c_int
     L.tor_debug_sampled_terms.argtypes = [vp, i32, i64, i32, vp, i64, vp, vp]
     L.tor_last_kernel_ms.restype = ctypes.c_double
-    L.tor_last_kernel_ms.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.tor_last_kernel_ms.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.tor_next_mask.restype = u64
     L.tor_next_mask.argtypes = [u64]
     L.tor_kth_mask.restype = u64

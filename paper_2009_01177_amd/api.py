@@ -149,11 +149,13 @@ def tor_debug_sampled_terms(O, masks, tier="dd", stream=None) -> np.ndarray:
 
 
 def tor_last_kernel_ms():
-    """(ms, split_depth, grid) of the last timed subset-tree kernel."""
+    """(ms, split_depth, grid, launches) of the dominant kernel in the last
+    timed evaluation; ms is the sum over its launches."""
     d = ctypes.c_int32(-1)
     gr = ctypes.c_int32(-1)
-    ms = lib().tor_last_kernel_ms(ctypes.byref(d), ctypes.byref(gr))
-    return float(ms), int(d.value), int(gr.value)
+    nl = ctypes.c_int32(0)
+    ms = lib().tor_last_kernel_ms(ctypes.byref(d), ctypes.byref(gr), ctypes.byref(nl))
+    return float(ms), int(d.value), int(gr.value), int(nl.value)
 
 
 # ---- host scheduling helpers (no GPU) -------------------------------------

@@ -33,10 +33,10 @@ struct Workspace {
   tor_result_t* host_res = nullptr;  // pinned
   double* host_lev = nullptr;        // pinned, 4*(TOR_NMAX+1)
   std::map<std::pair<int, int>, ItemTable> tables;  // (n, d) -> prefix items
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;  // kernel timing (TOR_FLAG_TIME_KERNEL)
-  bool timed = false;                        // events of the last launch are valid
+  std::vector<hipEvent_t> evs;  // kernel timing (TOR_FLAG_TIME_KERNEL): start/stop pairs
+  int ev_pairs = 0;             // pairs recorded by the last evaluation
   double last_ms = -1.0;
-  int last_d = -1, last_grid = -1;
+  int last_d = -1, last_grid = -1, last_launches = 0;
 };
 
 std::mutex g_mu;
@@ -50,6 +50,32 @@ inline int hip_err(hipError_t e) { return e == hipSuccess ? TOR_OK : (e == hipEr
     if (rc__ != TOR_OK) return rc__;    \
   } while (0)
 #define TOR_HIP(expr) TOR_TRY(hip_err(expr))
+
+// Record the start (k even) or stop (k odd) event of timed launch k/2.
+int record_ev(Workspace* w, int k, hipStream_t s) {
+  while ((int)w->evs.size() <= k) {
+    hipEvent_t e;
+    TOR_HIP(hipEventCreate(&e));
+    w->evs.push_back(e);
+  }
+  TOR_HIP(hipEventRecord(w->evs[k], s));
+  return TOR_OK;
+}
+
+// Sum the recorded launch durations (after the stream has synchronised).
+int collect_ev(Workspace* w) {
+  double tot = 0.0;
+  for (int p = 0; p < w->ev_pairs; ++p) {
+    float ms = 0.0f;
+    TOR_HIP(hipEventElapsedTime(&ms, w->evs[2 * p], w->evs[2 * p + 1]));
+    tot += ms;
+  }
+  w->last_ms = w->ev_pairs > 0 ? tot : -1.0;
+  w->last_launches = w->ev_pairs;
+  w->ev_pairs = 0;
+  return TOR_OK;
+}
+
 
 int get_ws(Workspace** out) {
   int dev = 0;
@@ -218,14 +244,13 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
   bl.partials = w->buf + o_part;
   bl.status = (int32_t*)(cnt + 1);
   const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
-  if (timed) {
-    if (!w->ev0) TOR_HIP(hipEventCreate(&w->ev0));
-    if (!w->ev1) TOR_HIP(hipEventCreate(&w->ev1));
-    TOR_HIP(hipEventRecord(w->ev0, s));
-  }
+  w->ev_pairs = 0;
+  if (timed) TOR_TRY(record_ev(w, 0, s));
   TOR_HIP(launch_border(bl, s));
-  if (timed) TOR_HIP(hipEventRecord(w->ev1, s));
-  w->timed = timed;
+  if (timed) {
+    TOR_TRY(record_ev(w, 1, s));
+    w->ev_pairs = 1;
+  }
   w->last_d = d;
   w->last_grid = grid;
   TOR_HIP(launch_reduce_cols(tier, w->buf + o_part, nitems, ncols, w->buf + o_red, s));
@@ -292,11 +317,7 @@ int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
 
   TOR_HIP(launch_zero_words(cnt, 64, s));
   const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
-  if (timed) {
-    if (!w->ev0) TOR_HIP(hipEventCreate(&w->ev0));
-    if (!w->ev1) TOR_HIP(hipEventCreate(&w->ev1));
-    TOR_HIP(hipEventRecord(w->ev0, s));
-  }
+  w->ev_pairs = 0;
   // stage 0: root, then breadth-first to depth D_c into the roots buffer
   {
     int cur = 0;
@@ -331,11 +352,14 @@ int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
     const void* lm = cur < 0 ? (const void*)im : (const void*)(B + o_m[cur]);
     const void* lg = cur < 0 ? (const void*)ig : (const void*)(B + o_g[cur]);
     const int32_t* ln = cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]);
+    if (timed) TOR_TRY(record_ev(w, 2 * ch, s));
     TOR_HIP(launch_leaf(tier, s_m, s_b, lm, lg, ln, (int)mids, n, B + o_part, status, grid, s));
+    if (timed) {
+      TOR_TRY(record_ev(w, 2 * ch + 1, s));
+      w->ev_pairs = ch + 1;
+    }
     TOR_HIP(launch_reduce_cols(tier, B + o_part, (int)mids, 2, B + o_chunk + ab * 2 * ch, s));
   }
-  if (timed) TOR_HIP(hipEventRecord(w->ev1, s));
-  w->timed = timed;
   w->last_d = D_m;
   w->last_grid = grid;
   TOR_HIP(launch_reduce_cols(tier, B + o_chunk, nchunks, 2, B + o_red, s));
@@ -385,8 +409,7 @@ int tor_shutdown(void) {
       if (w->buf) (void)hipFree(w->buf);
       if (w->host_res) (void)hipHostFree(w->host_res);
       if (w->host_lev) (void)hipHostFree(w->host_lev);
-      if (w->ev0) (void)hipEventDestroy(w->ev0);
-      if (w->ev1) (void)hipEventDestroy(w->ev1);
+      for (hipEvent_t e : w->evs) (void)hipEventDestroy(e);
       (void)hipSetDevice(cur);
     }
     delete w;
@@ -415,20 +438,17 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
     TOR_TRY(enqueue_schur(w, O, n, ld, tier, opt, s, &ro));
   TOR_HIP(hipMemcpyAsync(w->host_res, ro.dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
   TOR_HIP(hipStreamSynchronize(s));
-  if (w->timed) {
-    float ms = -1.0f;
-    TOR_HIP(hipEventElapsedTime(&ms, w->ev0, w->ev1));
-    w->last_ms = ms;
-  }
+  if (w->ev_pairs > 0) TOR_TRY(collect_ev(w));
   *out = *w->host_res;
   return out->status;
 }
 
-double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid) {
+double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches) {
   Workspace* w = nullptr;
   if (get_ws(&w) != TOR_OK) return -1.0;
   if (split_depth) *split_depth = w->last_d;
   if (grid) *grid = w->last_grid;
+  if (launches) *launches = w->last_launches;
   return w->last_ms;
 }
 
