@@ -27,10 +27,10 @@
 //   top    (HBM)  breadth-first expansion, one launch per decided mode, of
 //                 every state down to depth n - s_m; each state stores its
 //                 packed s_m-mode matrix, g and |Z|.
-//   middle (LDS)  one wavefront per depth-(n - s_m) state walks the subsets
-//                 of the next s_m - s_b modes depth-first; the updates are
-//                 spread over the lanes; each state reached at depth n - s_b
-//                 is handed to one lane.
+//   middle (LDS)  one wavefront per depth-(n - s_m) state expands the next
+//                 s_m - s_b <= 6 modes breadth-first, the entry updates of a
+//                 whole level spread over the lanes; the last of these
+//                 expansions gives each lane one state at depth n - s_b.
 //   bottom (VGPR) each lane finishes its own state: all 2^s_b subsets of the
 //                 last s_b modes, fully unrolled at compile time with the
 //                 matrices in registers.
@@ -255,32 +255,52 @@ __global__ __launch_bounds__(256) void expand_kernel(const typename TT::R* __res
 }
 
 // --------------------------------------------------------------------------
-// Middle + bottom: one wavefront per middle state (s_m undecided modes).
+// Middle + bottom: one wavefront per middle state of s_m undecided modes.
+//
+// The middle level expands the state breadth-first in LDS: level j holds
+// 2^j states of s_m - j modes (child 2z leaves the next mode out, 2z+1 takes
+// it in), so every barrier-separated phase has up to hundreds of
+// independent entry updates for the 64 lanes.  The last expansion is done by
+// each lane for its own state, straight into registers, and the bottom level
+// follows.  L = s_m - s_b <= 6 middle levels give up to 64 bottom states.
 // --------------------------------------------------------------------------
 
-template <class TT>
-struct MidFrame {
-  int base, s, m, i;
-  typename TT::R g;
-};
-
-// LDS layout of one wavefront (WG = 1 wavefront).
-template <class TT, int SM, int SB>
+template <class TT, int SB>
 struct MidSmem {
   using R = typename TT::R;
-  static constexpr int stack_vals() {
+  static constexpr int L = 6;
+  static constexpr int SM = SB + L;
+  // level j (s = SM - j modes, 2^j states): even levels in A, odd in B
+  static constexpr int level_vals(int j) { return (1 << j) * psize(SM - j); }
+  static constexpr int a_vals() {
     int v = 0;
-    for (int s = SM; s >= SB; s -= 2) v += psize(s);
+    for (int j = 0; j < L; j += 2) v = v > level_vals(j) ? v : level_vals(j);
     return v;
   }
-  static constexpr int max_frames = (SM - SB) + 2;
-  R stack[stack_vals()];
-  R u0[2 * SM], u1[2 * SM];
-  MidFrame<TT> frames[max_frames];
+  static constexpr int b_vals() {
+    int v = 0;
+    for (int j = 1; j < L; j += 2) v = v > level_vals(j) ? v : level_vals(j);
+    return v;
+  }
+  // pivot columns of the LDS expansions (levels 0 .. L-2)
+  static constexpr int u_vals() {
+    int v = 0;
+    for (int j = 0; j + 1 < L; ++j) {
+      const int w = (1 << j) * 2 * (SM - j - 1);
+      v = v > w ? v : w;
+    }
+    return v;
+  }
+  R A[a_vals()];
+  R B[b_vals()];
+  R gA[32], gB[32];
+  R rl0[16], l10[16], rl1[16];
+  R u0[u_vals()], u1[u_vals()];
+  int32_t mA[32], mB[32];
   uint16_t pairs[psize(SM)];  // packed index -> (row << 8) | col
 };
 
-template <class TT, int SM, int SB>
+template <class TT, int SB>
 __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restrict__ mat,
                                                   const typename TT::R* __restrict__ gin,
                                                   const int32_t* __restrict__ min_, int s_m,
@@ -289,134 +309,119 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
                                                   int32_t* __restrict__ status) {
   using R = typename TT::R;
   using Acc = typename TT::Acc;
-  __shared__ MidSmem<TT, SM, SB> sm;
+  using SMEM = MidSmem<TT, SB>;
+  __shared__ SMEM sm;
   const int lane = threadIdx.x;
-  for (int e = lane; e < psize(SM); e += 64) {
+  for (int e = lane; e < psize(SMEM::SM); e += 64) {
     int r = 0;
     while (pk(r + 1, 0) <= e) ++r;
     sm.pairs[e] = (uint16_t)((r << 8) | (e - pk(r, 0)));
   }
+  const int L = s_m - SB;  // middle levels, 0..6
   bool bad = false;
 
   for (int z = blockIdx.x; z < nstates; z += gridDim.x) {
     __syncthreads();
     const R* src = mat + (size_t)z * psize(s_m);
-    for (int e = lane; e < psize(s_m); e += 64) sm.stack[e] = src[e];
+    for (int e = lane; e < psize(s_m); e += 64) sm.A[e] = src[e];
+    if (lane == 0) {
+      sm.gA[0] = gin[z];
+      sm.mA[0] = min_[z];
+    }
+    __syncthreads();
+
+    // levels 0 .. L-1 in LDS
+    R* cur = sm.A;
+    R* nxt = sm.B;
+    R* cg = sm.gA;
+    R* ng = sm.gB;
+    int32_t* cm = sm.mA;
+    int32_t* nm = sm.mB;
+    for (int j = 0; j + 1 < L; ++j) {
+      const int S = s_m - j;  // modes of level j
+      const int ns = 1 << j;
+      const int ps = psize(S), pc = psize(S - 1);
+      const int rows = 2 * (S - 1);
+      if (lane < ns) {
+        const R* T = cur + lane * ps;
+        const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+        if (!pv.ok) bad = true;
+        sm.rl0[lane] = pv.rl0;
+        sm.l10[lane] = pv.l10;
+        sm.rl1[lane] = pv.rl1;
+        ng[2 * lane] = cg[lane];
+        nm[2 * lane] = cm[lane];
+        ng[2 * lane + 1] = r_mul(r_mul(cg[lane], pv.rl0), pv.rl1);
+        nm[2 * lane + 1] = cm[lane] + 1;
+      }
+      __syncthreads();
+      for (int idx = lane; idx < ns * rows; idx += 64) {
+        const int zz = idx / rows, a = idx - zz * rows;
+        const R* T = cur + zz * ps;
+        const R u0 = r_mul(T[pk(a + 2, 0)], sm.rl0[zz]);
+        sm.u0[zz * rows + a] = u0;
+        sm.u1[zz * rows + a] = r_mul(r_fms(T[pk(a + 2, 1)], u0, sm.l10[zz]), sm.rl1[zz]);
+      }
+      __syncthreads();
+      for (int idx = lane; idx < ns * pc; idx += 64) {
+        const int zz = idx / pc, e = idx - zz * pc;
+        const int pr = sm.pairs[e];
+        const int a = pr >> 8, b = pr & 255;
+        const R t = cur[zz * ps + pk(a + 2, b + 2)];
+        const R* u0 = sm.u0 + zz * rows;
+        const R* u1 = sm.u1 + zz * rows;
+        nxt[(2 * zz) * pc + e] = t;
+        nxt[(2 * zz + 1) * pc + e] = r_fms(r_fms(t, u0[a], u0[b]), u1[a], u1[b]);
+      }
+      __syncthreads();
+      R* t0 = cur; cur = nxt; nxt = t0;
+      R* t1 = cg; cg = ng; ng = t1;
+      int32_t* t2 = cm; cm = nm; nm = t2;
+    }
+
+    // last middle level: each lane forms its own bottom state in registers
     LaneAcc<TT> acc;
     acc.t = TT::acc_zero();
     acc.a = TT::acc_zero();
-    R leaf[psize(SB)];  // this lane's bottom-level state
+    const int nleaves = 1 << L;
+    if (lane < nleaves) {
+      R leaf[psize(SB)];
+      R lg;
+      int lm;
+      if (L == 0) {
 #pragma unroll
-    for (int e = 0; e < psize(SB); ++e) leaf[e] = r_zero<R>();
-    R leaf_g = r_zero<R>();
-    int leaf_m = 0;
-    int nleaf = 0;
-    int sp = 0;
-    if (lane == 0 && s_m > SB) {
-      MidFrame<TT> f;
-      f.base = 0;
-      f.s = s_m;
-      f.m = min_[z];
-      f.i = s_m - SB - 1;
-      f.g = gin[z];
-      sm.frames[0] = f;
-    }
-    __syncthreads();
-    // the pending state to hand to a lane: trailing SB modes of (base, s)
-    bool have = true, finished = (s_m == SB);
-    int p_base = 0, p_s = s_m, p_m = min_[z];
-    R p_g = gin[z];
-
-    for (;;) {
-      if (have) {
-        const int o = 2 * (p_s - SB);
+        for (int e = 0; e < psize(SB); ++e) leaf[e] = cur[e];
+        lg = cg[0];
+        lm = cm[0];
+      } else {
+        const int zz = lane >> 1;
+        const R* T = cur + zz * psize(SB + 1);
+        if ((lane & 1) == 0) {
 #pragma unroll
-        for (int a = 0; a < 2 * SB; ++a) {
+          for (int a = 0; a < 2 * SB; ++a)
 #pragma unroll
-          for (int b = 0; b <= a; ++b) {
-            const R v = sm.stack[p_base + pk(a + o, b + o)];
-            if (lane == nleaf) leaf[pk(a, b)] = v;
-          }
-        }
-        if (lane == nleaf) {
-          leaf_g = p_g;
-          leaf_m = p_m;
-        }
-        ++nleaf;
-        have = false;
-      }
-      if (nleaf == 64 || (finished && nleaf > 0)) {
-        if (lane < nleaf) Bottom<TT, SB>::run(leaf, leaf_g, leaf_m, n, acc, bad);
-        nleaf = 0;
-      }
-      if (finished) break;
-
-      // one step of the middle-level depth-first walk
-      const MidFrame<TT> f = sm.frames[sp];
-      if (f.i < 0) {
-        --sp;
-        if (sp < 0) finished = true;
-        continue;
-      }
-      const int i = f.i;
-      const int sc = f.s - 1 - i;  // undecided modes of the child
-      const int dst = (i > 0) ? f.base + psize(f.s) : f.base;
-      const int o = 2 * i + 2;
-      const R* T = sm.stack + f.base;
-      const Pivot<R> pv = make_pivot(T[pk(2 * i, 2 * i)], T[pk(2 * i + 1, 2 * i)],
-                                     T[pk(2 * i + 1, 2 * i + 1)]);
-      if (!pv.ok) bad = true;
-      const R gc = r_mul(r_mul(f.g, pv.rl0), pv.rl1);
-      if (lane < 2 * sc) {
-        const R u0 = r_mul(T[pk(lane + o, 2 * i)], pv.rl0);
-        sm.u0[lane] = u0;
-        sm.u1[lane] = r_mul(r_fms(T[pk(lane + o, 2 * i + 1)], u0, pv.l10), pv.rl1);
-      }
-      __syncthreads();
-      // child entries; in place (i == 0) is safe: entry e reads index > e
-      R* C = sm.stack + dst;
-      const int ne = psize(sc);
-      for (int e0 = 0; e0 < ne; e0 += 64) {
-        const int e = e0 + lane;
-        R v = r_zero<R>();
-        if (e < ne) {
-          const int pr = sm.pairs[e];
-          const int a = pr >> 8, b = pr & 255;
-          v = r_fms(r_fms(T[pk(a + o, b + o)], sm.u0[a], sm.u0[b]), sm.u1[a], sm.u1[b]);
-        }
-        __syncthreads();
-        if (e < ne) C[e] = v;
-      }
-      if (lane == 0) {
-        if (sc == SB) {
-          sm.frames[sp].i = i - 1;
+            for (int b = 0; b <= a; ++b) leaf[pk(a, b)] = T[pk(a + 2, b + 2)];
+          lg = cg[zz];
+          lm = cm[zz];
         } else {
-          MidFrame<TT> cf;
-          cf.base = dst;
-          cf.s = sc;
-          cf.m = f.m + 1;
-          cf.i = sc - SB - 1;
-          cf.g = gc;
-          if (i > 0) {
-            sm.frames[sp].i = i - 1;
-            sm.frames[sp + 1] = cf;
-          } else {
-            sm.frames[sp] = cf;
+          const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+          if (!pv.ok) bad = true;
+          R u0[2 * SB], u1[2 * SB];
+#pragma unroll
+          for (int a = 0; a < 2 * SB; ++a) {
+            u0[a] = r_mul(T[pk(a + 2, 0)], pv.rl0);
+            u1[a] = r_mul(r_fms(T[pk(a + 2, 1)], u0[a], pv.l10), pv.rl1);
           }
+#pragma unroll
+          for (int a = 0; a < 2 * SB; ++a)
+#pragma unroll
+            for (int b = 0; b <= a; ++b)
+              leaf[pk(a, b)] = r_fms(r_fms(T[pk(a + 2, b + 2)], u0[a], u0[b]), u1[a], u1[b]);
+          lg = r_mul(r_mul(cg[zz], pv.rl0), pv.rl1);
+          lm = cm[zz] + 1;
         }
       }
-      if (sc != SB && i > 0) ++sp;
-      if (sc == SB && i == 0) {
-        // the frame's last child was a leaf: the frame is done
-        --sp;
-      }
-      __syncthreads();
-      have = true;
-      p_base = dst;
-      p_s = sc;
-      p_m = f.m + 1;
-      p_g = gc;
-      if (sp < 0) finished = true;
+      Bottom<TT, SB>::run(leaf, lg, lm, n, acc, bad);
     }
     // fixed-order butterfly over the wave, then one partial per state
     Acc t = acc.t, a = acc.a;
@@ -447,12 +452,11 @@ size_t schur_value_bytes(int tier) {
 }
 
 void schur_levels(int tier, int n, int* s_m, int* s_b) {
-  // bottom size by register budget; middle size by LDS budget
+  // bottom size by register budget; six middle levels (64 bottom states)
   int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
-  int smx = tier == TOR_QD ? 10 : 12;
   if (sb > n) sb = n;
-  int sm = smx < n ? smx : n;
-  if (sm < sb) sm = sb;
+  int sm = sb + 6;
+  if (sm > n) sm = n;
   *s_m = sm;
   *s_b = sb;
 }
@@ -496,79 +500,63 @@ hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const i
   return hipGetLastError();
 }
 
-template <class TT, int SM, int SB>
+template <class TT, int SB>
 static hipError_t launch_leaf_t(const void* mat, const void* g, const int32_t* m, int s_m, int nst,
                                 int n, void* partials, int32_t* status, int grid, hipStream_t st) {
   using R = typename TT::R;
   using Acc = typename TT::Acc;
-  hipLaunchKernelGGL((leaf_kernel<TT, SM, SB>), dim3(grid), dim3(64), 0, st, (const R*)mat,
-                     (const R*)g, m, s_m, nst, n, (Acc*)partials, status);
+  hipLaunchKernelGGL((leaf_kernel<TT, SB>), dim3(grid), dim3(64), 0, st, (const R*)mat, (const R*)g,
+                     m, s_m, nst, n, (Acc*)partials, status);
   return hipGetLastError();
 }
 
-template <class TT, int SM, int SB>
+template <class TT, int SB>
 static const void* leaf_fn() {
-  return reinterpret_cast<const void*>(&leaf_kernel<TT, SM, SB>);
+  return reinterpret_cast<const void*>(&leaf_kernel<TT, SB>);
 }
 
-// Dispatch over the compiled (tier, s_b) combinations; s_m is the LDS
-// capacity of the middle level (a runtime s_m <= SM is allowed).
-#define TOR_LEAF_CASES(TT, SMX)                                                        \
-  switch (s_b) {                                                                       \
-    case 1: return CALL(TT, SMX, 1);                                                   \
-    case 2: return CALL(TT, SMX, 2);                                                   \
-    case 3: return CALL(TT, SMX, 3);                                                   \
-    case 4: return CALL(TT, SMX, 4);                                                   \
-    case 5: return CALL(TT, SMX, 5);                                                   \
-    default: break;                                                                    \
-  }
+// Compiled (tier, s_b) combinations: s_b is the tier's register budget, or n
+// when n is smaller.
+#define TOR_LEAF_DISPATCH(CALL)                                   \
+  if (tier == TOR_FP64) {                                         \
+    switch (s_b) {                                                \
+      case 1: return CALL(TierF64, 1);                            \
+      case 2: return CALL(TierF64, 2);                            \
+      case 3: return CALL(TierF64, 3);                            \
+      case 4: return CALL(TierF64, 4);                            \
+      case 5: return CALL(TierF64, 5);                            \
+      default: break;                                             \
+    }                                                             \
+  } else if (tier == TOR_DD) {                                    \
+    switch (s_b) {                                                \
+      case 1: return CALL(TierDD, 1);                             \
+      case 2: return CALL(TierDD, 2);                             \
+      case 3: return CALL(TierDD, 3);                             \
+      case 4: return CALL(TierDD, 4);                             \
+      default: break;                                             \
+    }                                                             \
+  } else {                                                        \
+    switch (s_b) {                                                \
+      case 1: return CALL(TierQD, 1);                             \
+      case 2: return CALL(TierQD, 2);                             \
+      default: break;                                             \
+    }                                                             \
+  }                                                               \
+  return hipErrorInvalidValue;
 
 hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
                        int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st) {
-#define CALL(TT, SMX, SBV) launch_leaf_t<TT, SMX, SBV>(mat, g, m, s_m, nst, n, partials, status, grid, st)
-  if (tier == TOR_FP64) {
-    TOR_LEAF_CASES(TierF64, 12)
-  } else if (tier == TOR_DD) {
-    switch (s_b) {
-      case 1: return CALL(TierDD, 12, 1);
-      case 2: return CALL(TierDD, 12, 2);
-      case 3: return CALL(TierDD, 12, 3);
-      case 4: return CALL(TierDD, 12, 4);
-      default: break;
-    }
-  } else {
-    switch (s_b) {
-      case 1: return CALL(TierQD, 10, 1);
-      case 2: return CALL(TierQD, 10, 2);
-      default: break;
-    }
-  }
+  if (s_m < s_b || s_m - s_b > 6) return hipErrorInvalidValue;
+#define CALL(TT, SBV) launch_leaf_t<TT, SBV>(mat, g, m, s_m, nst, n, partials, status, grid, st)
+  TOR_LEAF_DISPATCH(CALL)
 #undef CALL
-  return hipErrorInvalidValue;
 }
 
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu) {
-#define CALL(TT, SMX, SBV) hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, leaf_fn<TT, SMX, SBV>(), 64, 0)
-  if (tier == TOR_FP64) {
-    TOR_LEAF_CASES(TierF64, 12)
-  } else if (tier == TOR_DD) {
-    switch (s_b) {
-      case 1: return CALL(TierDD, 12, 1);
-      case 2: return CALL(TierDD, 12, 2);
-      case 3: return CALL(TierDD, 12, 3);
-      case 4: return CALL(TierDD, 12, 4);
-      default: break;
-    }
-  } else {
-    switch (s_b) {
-      case 1: return CALL(TierQD, 10, 1);
-      case 2: return CALL(TierQD, 10, 2);
-      default: break;
-    }
-  }
+#define CALL(TT, SBV) hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, leaf_fn<TT, SBV>(), 64, 0)
+  TOR_LEAF_DISPATCH(CALL)
 #undef CALL
-  return hipErrorInvalidValue;
 }
-#undef TOR_LEAF_CASES
+#undef TOR_LEAF_DISPATCH
 
 }  // namespace tor
