@@ -92,10 +92,10 @@ def paper_eq9_flops(n: int) -> float:
     return sum(math.comb(n, i) * (32.0 / 3 * i ** 3 + 4 * i * i - 8.0 / 3 * i) for i in range(1, n + 1))
 
 
-def time_tier(tor, Od, tier, steps, warmup, algo="auto", split=-1):
+def time_tier(tor, Od, tier, steps, warmup, algo="auto", split=-1, sb=0):
     import torch
     for _ in range(warmup):
-        tor.tor_eval(Od, tier=tier, algo=algo, split_depth=split, time_kernel=True)
+        tor.tor_eval(Od, tier=tier, algo=algo, split_depth=split, time_kernel=True, bottom_modes=sb)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
@@ -103,7 +103,8 @@ def time_tier(tor, Od, tier, steps, warmup, algo="auto", split=-1):
     res = None
     t0.record()
     for _ in range(steps):
-        res = tor.tor_eval(Od, tier=tier, algo=algo, split_depth=split, time_kernel=True)
+        res = tor.tor_eval(Od, tier=tier, algo=algo, split_depth=split, time_kernel=True,
+                           bottom_modes=sb)
         kms.append(tor.tor_last_kernel_ms())
     t1.record()
     torch.cuda.synchronize()
@@ -146,6 +147,8 @@ def main():
     ap.add_argument("--tier", default="dd", choices=["dd", "fp64"])
     ap.add_argument("--algo", default="auto")
     ap.add_argument("--split", type=int, default=-1)
+    ap.add_argument("--sb", type=int, default=0, help="Schur path: bottom modes per lane (0 = default)")
+    ap.add_argument("--sb-other", type=int, default=0)
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -170,7 +173,7 @@ def main():
           flush=True)
 
     algo = "border" if args.algo == "border" else "schur"
-    ms, kms, res = time_tier(tor, Od, args.tier, args.steps, args.warmup, algo, args.split)
+    ms, kms, res = time_tier(tor, Od, args.tier, args.steps, args.warmup, algo, args.split, args.sb)
     terms = float(1 << n)
     value = terms / (ms / 1e3)
     kernel_ms = float(np.mean([k[0] for k in kms]))  # sum over the step's launches
@@ -181,7 +184,7 @@ def main():
           f"{value:.3e} terms/s, {achieved:.2f} TFLOP/s", file=sys.stderr, flush=True)
 
     other = "fp64" if args.tier == "dd" else "dd"
-    oms, okms, ores = time_tier(tor, Od, other, args.fp64_steps, 1, algo, args.split)
+    oms, okms, ores = time_tier(tor, Od, other, args.fp64_steps, 1, algo, args.split, args.sb_other)
     okernel = float(np.mean([k[0] for k in okms]))
     oflops = kernel_flops(n, other, algo, okms[-1][1])
     print(f"[bench] {other}: {oms:.3f} ms/step, kernel {okernel:.3f} ms", file=sys.stderr, flush=True)

@@ -87,11 +87,15 @@ typedef struct tor_result {
 
 /* Optional knobs; pass NULL for defaults. */
 typedef struct tor_options {
-  int32_t algo;        /* tor_algo_t */
-  int32_t split_depth; /* d: number of leading modes whose subsets form the
-                          work items (2^d of them); -1 = autotuned */
-  int32_t grid;        /* persistent workgroups; 0 = from occupancy */
-  int32_t flags;       /* TOR_FLAG_* bits */
+  int32_t algo;         /* tor_algo_t */
+  int32_t split_depth;  /* TOR_ALGO_BORDER: d, the number of leading modes
+                           whose subsets form the work items (2^d of them);
+                           -1 = automatic */
+  int32_t grid;         /* persistent workgroups; 0 = from occupancy */
+  int32_t flags;        /* TOR_FLAG_* bits */
+  int32_t bottom_modes; /* TOR_ALGO_SCHUR: modes each lane finishes in
+                           registers (s_b); 0 = the tier's default */
+  int32_t reserved[3];
 } tor_options_t;
 
 /* Record HIP events around the subset-tree kernel (on the caller's stream);

@@ -42,6 +42,8 @@ class TorOptionsC(ctypes.Structure):
         ("split_depth", ctypes.c_int32),
         ("grid", ctypes.c_int32),
         ("flags", ctypes.c_int32),
+        ("bottom_modes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -104,11 +104,12 @@ def tor_shutdown():
 
 
 def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
-             stream=None, raise_on_error: bool = True, time_kernel: bool = False) -> TorResult:
+             stream=None, raise_on_error: bool = True, time_kernel: bool = False,
+             bottom_modes: int = 0) -> TorResult:
     """Tor(O) of one instance (synchronous)."""
     Od, n, ld = _device_o(O)
     flags = _lib.TOR_FLAG_TIME_KERNEL if time_kernel else 0
-    opt = _lib.TorOptionsC(algo_id(algo), int(split_depth), int(grid), flags)
+    opt = _lib.TorOptionsC(algo_id(algo), int(split_depth), int(grid), flags, int(bottom_modes))
     out = _lib.TorResultC()
     rc = lib().tor_eval(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), ctypes.byref(opt),
                         _stream_ptr(stream), ctypes.byref(out))

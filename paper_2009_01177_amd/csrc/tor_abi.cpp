@@ -272,7 +272,7 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
 int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
                   const tor_options_t* opt, hipStream_t s, RunOut* ro) {
   int s_m = 0, s_b = 0;
-  schur_levels(tier, n, &s_m, &s_b);
+  schur_levels(tier, n, opt ? opt->bottom_modes : 0, &s_m, &s_b);
   const int D_m = n - s_m;
   const int LT = 17;
   const int D_c = D_m > LT ? D_m - LT : 0;

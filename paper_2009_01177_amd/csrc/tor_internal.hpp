@@ -57,7 +57,7 @@ hipError_t launch_expand_terms(int tier, const void* partials, int nitems, doubl
 // ---- right-looking Schur-complement kernels (tor_schur.hip) ----
 size_t schur_value_bytes(int tier);
 // middle-level (s_m) and bottom-level (s_b) mode counts for a tier and n
-void schur_levels(int tier, int n, int* s_m, int* s_b);
+void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b);
 hipError_t launch_real_root(int tier, const double2* O, int n, int64_t ld, void* mat, void* g,
                             int32_t* m, hipStream_t s);
 hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,

@@ -451,9 +451,11 @@ size_t schur_value_bytes(int tier) {
   return tier == TOR_FP64 ? sizeof(double) : (tier == TOR_DD ? sizeof(dd) : sizeof(qd));
 }
 
-void schur_levels(int tier, int n, int* s_m, int* s_b) {
+void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b) {
   // bottom size by register budget; six middle levels (64 bottom states)
+  const int sb_max = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
   int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
+  if (sb_req > 0) sb = sb_req < sb_max ? sb_req : sb_max;
   if (sb > n) sb = n;
   int sm = sb + 6;
   if (sm > n) sm = n;
