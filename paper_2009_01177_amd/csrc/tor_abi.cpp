@@ -221,6 +221,7 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
   const size_t o_oi = c.take(sizeof(double2) * 4 * (size_t)n * n);
   const size_t o_part = c.take(ab * (size_t)nitems * ncols);
   const size_t o_red = c.take(ab * (size_t)ncols);
+  const size_t o_rsc = c.take(reduce_scratch_bytes(tier, nitems, ncols));
   const size_t o_cnt = c.take(sizeof(uint32_t) * 64);
   const size_t o_res = c.take(sizeof(tor_result_t));
   TOR_TRY(ensure_cap(w, c.off));
@@ -253,7 +254,7 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
   }
   w->last_d = d;
   w->last_grid = grid;
-  TOR_HIP(launch_reduce_cols(tier, w->buf + o_part, nitems, ncols, w->buf + o_red, s));
+  TOR_HIP(launch_reduce_cols(tier, w->buf + o_part, nitems, ncols, w->buf + o_red, w->buf + o_rsc, s));
   const double err_rel = (double)(4 * n * n + d + 8) * unit_roundoff(tier);
   TOR_HIP(launch_finalize(tier, w->buf + o_red, (const int32_t*)(cnt + 1), err_rel,
                           (tor_result_t*)(w->buf + o_res), s));
@@ -265,34 +266,41 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
 
 
 // Right-looking Schur-complement evaluation (MODE_SUM only).
-//   depth 0 -> D_c : breadth-first in HBM, all states kept ("roots")
-//   per root       : breadth-first D_c -> D_m = n - s_m, then the middle +
-//                    bottom kernel over the 2^(D_m - D_c) middle states
-// D_c is chosen so that one root's expansion has at most 2^17 middle states.
+//   depth 0 -> D_s : breadth-first in HBM, all states kept ("roots")
+//   per chunk      : Cr consecutive roots expanded breadth-first to depth
+//                    D_m = n - s_m, then the middle + bottom kernel over the
+//                    Cr 2^(D_m - D_s) middle states
+// A chunk's last top level is kept near 1.5 GB.
 int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
                   const tor_options_t* opt, hipStream_t s, RunOut* ro) {
   int s_m = 0, s_b = 0;
   schur_levels(tier, n, opt ? opt->bottom_modes : 0, &s_m, &s_b);
   const int D_m = n - s_m;
-  const int LT = 17;
-  const int D_c = D_m > LT ? D_m - LT : 0;
-  const int Dl = D_m - D_c;  // levels expanded per root
-  const int nchunks = 1 << D_c;
   const size_t rb = schur_value_bytes(tier);
   const size_t ab = acc_bytes(tier);
   auto ps = [](int k) { return (size_t)k * (2 * k + 1); };
+  // middle states per chunk: about 1.5 GB of them at the last top level
+  int LT = 0;
+  while (LT < 22 && ((size_t)2 << LT) * ps(s_m) * rb <= ((size_t)3 << 29)) ++LT;
+  // stage 0 keeps every state of depth D_s; a chunk expands Cr of them
+  int D_s = D_m < 10 ? D_m : 10;
+  if (D_m - D_s > LT) D_s = D_m - LT;
+  const int Dl = D_m - D_s;  // levels expanded per chunk
+  const int lcr = std::min(D_s, LT - Dl);
+  const int Cr = 1 << lcr;             // roots per chunk
+  const int nchunks = 1 << (D_s - lcr);
+  const int D_c = D_s;
 
-  // largest level of the stage-0 and per-root expansions
   size_t lvl_vals = ps(n);
-  for (int j = 1; j <= D_c; ++j) lvl_vals = std::max(lvl_vals, ((size_t)1 << j) * ps(n - j));
-  for (int j = 1; j <= Dl; ++j) lvl_vals = std::max(lvl_vals, ((size_t)1 << j) * ps(n - D_c - j));
-  const size_t lvl_states = (size_t)1 << std::max(D_c, Dl);
-  const size_t mids = (size_t)1 << Dl;
+  for (int j = 1; j <= D_s; ++j) lvl_vals = std::max(lvl_vals, ((size_t)1 << j) * ps(n - j));
+  for (int j = 1; j <= Dl; ++j) lvl_vals = std::max(lvl_vals, ((size_t)Cr << j) * ps(n - D_s - j));
+  const size_t lvl_states = std::max((size_t)1 << D_s, (size_t)Cr << Dl);
+  const size_t mids = (size_t)Cr << Dl;
 
   Carver c;
-  const size_t o_rm = c.take(rb * ((size_t)nchunks * ps(n - D_c)));
-  const size_t o_rg = c.take(rb * nchunks);
-  const size_t o_rn = c.take(sizeof(int32_t) * nchunks);
+  const size_t o_rm = c.take(rb * (((size_t)1 << D_s) * ps(n - D_s)));
+  const size_t o_rg = c.take(rb * ((size_t)1 << D_s));
+  const size_t o_rn = c.take(sizeof(int32_t) * ((size_t)1 << D_s));
   size_t o_m[2], o_g[2], o_n[2];
   for (int k = 0; k < 2; ++k) {
     o_m[k] = c.take(rb * lvl_vals);
@@ -302,6 +310,8 @@ int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
   const size_t o_part = c.take(ab * 2 * mids);
   const size_t o_chunk = c.take(ab * 2 * (size_t)nchunks);
   const size_t o_red = c.take(ab * 2);
+  const size_t o_rsc = c.take(std::max(reduce_scratch_bytes(tier, (int)mids, 2),
+                                       reduce_scratch_bytes(tier, nchunks, 2)));
   const size_t o_cnt = c.take(sizeof(uint32_t) * 64);
   const size_t o_res = c.take(sizeof(tor_result_t));
   TOR_TRY(ensure_cap(w, c.off));
@@ -335,17 +345,17 @@ int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
       cur = 1 - cur;
     }
   }
-  // per root: expand Dl levels, then the middle + bottom kernel
+  // per chunk of Cr roots: expand Dl levels, then the middle + bottom kernel
   for (int ch = 0; ch < nchunks; ++ch) {
-    const char* im = B + o_rm + rb * ((size_t)ch * ps(n - D_c));
-    const char* ig = B + o_rg + rb * ch;
-    const int32_t* in_ = (const int32_t*)(B + o_rn) + ch;
-    int cur = -1;  // -1: the root itself
+    const char* im = B + o_rm + rb * ((size_t)ch * Cr * ps(n - D_c));
+    const char* ig = B + o_rg + rb * ((size_t)ch * Cr);
+    const int32_t* in_ = (const int32_t*)(B + o_rn) + (size_t)ch * Cr;
+    int cur = -1;  // -1: the chunk's roots themselves
     for (int j = 0; j < Dl; ++j) {
       const int nx = (cur == 0) ? 1 : 0;
       TOR_HIP(launch_expand(tier, cur < 0 ? (const void*)im : (const void*)(B + o_m[cur]),
                             cur < 0 ? (const void*)ig : (const void*)(B + o_g[cur]),
-                            cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]), n - D_c - j, 1 << j,
+                            cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]), n - D_c - j, Cr << j,
                             B + o_m[nx], B + o_g[nx], (int32_t*)(B + o_n[nx]), status, s));
       cur = nx;
     }
@@ -358,11 +368,11 @@ int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
       TOR_TRY(record_ev(w, 2 * ch + 1, s));
       w->ev_pairs = ch + 1;
     }
-    TOR_HIP(launch_reduce_cols(tier, B + o_part, (int)mids, 2, B + o_chunk + ab * 2 * ch, s));
+    TOR_HIP(launch_reduce_cols(tier, B + o_part, (int)mids, 2, B + o_chunk + ab * 2 * ch, B + o_rsc, s));
   }
   w->last_d = D_m;
   w->last_grid = grid;
-  TOR_HIP(launch_reduce_cols(tier, B + o_chunk, nchunks, 2, B + o_red, s));
+  TOR_HIP(launch_reduce_cols(tier, B + o_chunk, nchunks, 2, B + o_red, B + o_rsc, s));
   const double err_rel = (double)(4 * n * n + n + 8) * unit_roundoff(tier);
   TOR_HIP(launch_finalize(tier, B + o_red, status, err_rel, (tor_result_t*)(B + o_res), s));
   ro->dres = (tor_result_t*)(B + o_res);

@@ -305,23 +305,32 @@ __global__ void zero_kernel(uint32_t* p, int count) {
   if (i < count) p[i] = 0u;
 }
 
+// Fixed-order reduction of part[nitems][ncols]: block (k, col) sums the
+// items of segment k = [k*SEG, (k+1)*SEG) -- thread t takes every 256th item
+// from k*SEG + t, then a tree over the 256 threads -- into red[k][col].  The
+// order depends only on SEG and the block size, never on the launch.
+constexpr int RED_SEG = 4096;
+
 template <class TT>
 __global__ __launch_bounds__(256) void reduce_cols_kernel(const typename TT::Acc* __restrict__ part,
                                                           int nitems, int ncols,
                                                           typename TT::Acc* __restrict__ red) {
   using Acc = typename TT::Acc;
   __shared__ Acc buf[256];
-  const int col = blockIdx.x;
+  const int seg = blockIdx.x;
+  const int col = blockIdx.y;
   const int tid = threadIdx.x;
+  const int lo = seg * RED_SEG;
+  const int hi = min(nitems, lo + RED_SEG);
   Acc a = TT::acc_zero();
-  for (int i = tid; i < nitems; i += 256) a = TT::acc_merge(a, part[(size_t)i * ncols + col]);
+  for (int i = lo + tid; i < hi; i += 256) a = TT::acc_merge(a, part[(size_t)i * ncols + col]);
   buf[tid] = a;
   __syncthreads();
   for (int s = 128; s >= 1; s >>= 1) {
     if (tid < s) buf[tid] = TT::acc_merge(buf[tid], buf[tid + s]);
     __syncthreads();
   }
-  if (tid == 0) red[col] = buf[0];
+  if (tid == 0) red[(size_t)seg * ncols + col] = buf[0];
 }
 
 __device__ inline void acc_store(const dd& a, double* out4) {
@@ -437,14 +446,29 @@ hipError_t launch_border(const BorderLaunch& a, hipStream_t s) {
   return hipLaunchKernel(fn, dim3(a.grid), dim3(64), args, lds, s);
 }
 
+template <class TT>
+static void reduce_stage(const void* part, int nitems, int ncols, void* out, hipStream_t s) {
+  using Acc = typename TT::Acc;
+  const int nseg = (nitems + RED_SEG - 1) / RED_SEG;
+  hipLaunchKernelGGL(reduce_cols_kernel<TT>, dim3(nseg > 0 ? nseg : 1, ncols), dim3(256), 0, s,
+                     (const Acc*)part, nitems, ncols, (Acc*)out);
+}
+
+size_t reduce_scratch_bytes(int tier, int nitems, int ncols) {
+  const size_t nseg = (size_t)(nitems + RED_SEG - 1) / RED_SEG;
+  return acc_bytes(tier) * (nseg > 1 ? nseg : 1) * ncols;
+}
+
 hipError_t launch_reduce_cols(int tier, const void* partials, int nitems, int ncols, void* red,
-                              hipStream_t s) {
+                              void* scratch, hipStream_t s) {
+  const bool two = nitems > RED_SEG;
+  const int nseg = (nitems + RED_SEG - 1) / RED_SEG;
   if (tier == TOR_QD) {
-    hipLaunchKernelGGL(reduce_cols_kernel<TierQD>, dim3(ncols), dim3(256), 0, s,
-                       (const qd*)partials, nitems, ncols, (qd*)red);
+    reduce_stage<TierQD>(partials, nitems, ncols, two ? scratch : red, s);
+    if (two) reduce_stage<TierQD>(scratch, nseg, ncols, red, s);
   } else {
-    hipLaunchKernelGGL(reduce_cols_kernel<TierDD>, dim3(ncols), dim3(256), 0, s,
-                       (const dd*)partials, nitems, ncols, (dd*)red);
+    reduce_stage<TierDD>(partials, nitems, ncols, two ? scratch : red, s);
+    if (two) reduce_stage<TierDD>(scratch, nseg, ncols, red, s);
   }
   return hipGetLastError();
 }

@@ -42,9 +42,12 @@ size_t border_lds_bytes(int tier, int mode, int n);
 hipError_t border_occupancy(int tier, int mode, int n, int* blocks_per_cu);
 hipError_t launch_border(const BorderLaunch& a, hipStream_t s);
 
-// Fixed-order reduction of partials [nitems][ncols] into red [ncols].
+// Fixed-order reduction of partials [nitems][ncols] into red [ncols]; for
+// more than 4096 items a first pass per 4096-item segment goes to scratch
+// (reduce_scratch_bytes).  The order never depends on the launch shape.
+size_t reduce_scratch_bytes(int tier, int nitems, int ncols);
 hipError_t launch_reduce_cols(int tier, const void* partials, int nitems, int ncols, void* red,
-                              hipStream_t s);
+                              void* scratch, hipStream_t s);
 
 // Build the tor_result_t from the two reduced columns (signed sum, |sum|).
 hipError_t launch_finalize(int tier, const void* red, const int32_t* status, double err_rel,

@@ -454,7 +454,7 @@ size_t schur_value_bytes(int tier) {
 void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b) {
   // bottom size by register budget; six middle levels (64 bottom states)
   const int sb_max = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
-  int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
+  int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 3 : 2);
   if (sb_req > 0) sb = sb_req < sb_max ? sb_req : sb_max;
   if (sb > n) sb = n;
   int sm = sb + 6;
