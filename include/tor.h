@@ -101,6 +101,10 @@ typedef struct tor_options {
 /* Record HIP events around the subset-tree kernel (on the caller's stream);
  * read the duration back with tor_last_kernel_ms(). */
 #define TOR_FLAG_TIME_KERNEL 1
+/* tor_eval_batched: capture the batch's launches in a HIP graph on first
+ * use and replay it when the same batch (same pointers, sizes, offsets and
+ * tiers) comes again. */
+#define TOR_FLAG_GRAPH 2
 
 /* Library version string. */
 const char* tor_version(void);
@@ -126,6 +130,29 @@ int tor_shutdown(void);
  * Synchronous: enqueues on `stream` and waits for it. */
 int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_options_t* opt,
              void* stream, tor_result_t* out);
+
+/* Torontonians of many instances of uneven n (the click patterns a sampler
+ * scores, Sec. 7.1.1: about a hundred per sample), enqueued on `stream`.
+ * Instances are grouped by (n, tier); each group's states are expanded
+ * together and the whole batch is one fixed sequence of launches, which
+ * TOR_FLAG_GRAPH captures once and replays.
+ *   O_packed  device; instance k's O (2n_k x 2n_k complex128, row-major,
+ *             leading dimension 2n_k, block order, lower triangle read)
+ *             starts at O_packed + offsets[k] complex elements
+ *   offsets   host, batch int64
+ *   n         host, batch int32, each 0..TOR_NMAX
+ *   tiers     host, batch int32 (TOR_FP64 / TOR_DD / TOR_QD / TOR_AUTO), or
+ *             NULL for all TOR_AUTO; TOR_AUTO instances get the cheapest
+ *             tier the precision selector expects to meet `tau`
+ *   tau       forward relative accuracy target |dTor| / |Tor| for TOR_AUTO
+ *   opt       NULL or knobs (algo must be TOR_ALGO_AUTO or TOR_ALGO_SCHUR)
+ *   out       device, batch results; status TOR_ENOTPD marks an instance
+ *             whose I - O is not positive definite
+ * The call waits for `stream` to drain, uploads the batch plan, then
+ * enqueues the evaluation and returns without waiting for it. */
+int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
+                     const int32_t* tiers, double tau, const tor_options_t* opt, void* stream,
+                     tor_result_t* out);
 
 /* Per-level sums L_m = sum over |Z| = m of det(I - O_Z)^(-1/2), m = 0..n
  * (the pieces Alg. 1's level loop adds up, each unsigned).

@@ -6,6 +6,6 @@ the library; the first call does, and raises if it is missing.
 """
 from ._lib import TorError, TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO  # noqa: F401
 from .api import (  # noqa: F401
-    TorResult, tor_version, tor_init, tor_shutdown, tor_eval, tor_debug_level_sums,
+    TorResult, Batch, tor_eval_batched, tor_version, tor_init, tor_shutdown, tor_eval, tor_debug_level_sums,
     tor_debug_sampled_terms, tor_last_kernel_ms, tor_next_mask, tor_kth_mask, tor_plan_items,
 )

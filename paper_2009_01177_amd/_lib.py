@@ -17,10 +17,11 @@ TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO = 0, 1, 2, -1
 TOR_ALGO_AUTO, TOR_ALGO_BORDER, TOR_ALGO_SCHUR = 0, 1, 2
 TOR_NMAX = 48
 TOR_FLAG_TIME_KERNEL = 1
+TOR_FLAG_GRAPH = 2
 
 # Every symbol include/tor.h declares.
 EXPORTS = (
-    "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval",
+    "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval", "tor_eval_batched",
     "tor_debug_level_sums", "tor_debug_sampled_terms", "tor_last_kernel_ms",
     "tor_next_mask", "tor_kth_mask", "tor_plan_items",
 )
@@ -84,6 +85,10 @@ def lib():
     L.tor_eval.restype = ctypes.c_int
     L.tor_eval.argtypes = [vp, i32, i64, i32, ctypes.POINTER(TorOptionsC), vp,
                            ctypes.POINTER(TorResultC)]
+    L.tor_eval_batched.restype = ctypes.c_int
+    L.tor_eval_batched.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), i32,
+                                   ctypes.POINTER(i32), ctypes.c_double, ctypes.POINTER(TorOptionsC),
+                                   vp, vp]
     L.tor_debug_level_sums.restype = ctypes.c_int
     L.tor_debug_level_sums.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
     L.tor_debug_sampled_terms.restype = ctypes.c_int

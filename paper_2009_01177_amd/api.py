@@ -118,6 +118,61 @@ def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
     return _res(out)
 
 
+class Batch:
+    """A packed batch on the device: instance k's O (2n_k x 2n_k, leading
+    dimension 2n_k) at offsets[k] complex elements into one buffer."""
+
+    def __init__(self, Os, device="cuda"):
+        torch = _torch()
+        self.n = np.array([o.shape[0] // 2 for o in Os], dtype=np.int32)
+        sizes = np.array([o.shape[0] * o.shape[0] for o in Os], dtype=np.int64)
+        self.offsets = np.zeros(len(Os), dtype=np.int64)
+        if len(Os):
+            self.offsets[1:] = np.cumsum(sizes)[:-1]
+        flat = np.concatenate([np.ascontiguousarray(o, dtype=np.complex128).ravel() for o in Os]) \
+            if len(Os) else np.zeros(1, dtype=np.complex128)
+        self.O = torch.from_numpy(flat).to(device)
+        self.batch = len(Os)
+        self.out = torch.zeros((max(self.batch, 1), 8), dtype=torch.float64, device=device)
+
+
+def _results_from(buf):
+    """Decode a (batch, 8) float64 view of tor_result_t records."""
+    raw = np.ascontiguousarray(buf).view(np.uint8)
+    res = []
+    for i in range(buf.shape[0]):
+        r = _lib.TorResultC.from_buffer_copy(raw[i].tobytes())
+        res.append(_res(r))
+    return res
+
+
+def tor_eval_batched(batch: "Batch", tiers=None, tau: float = 1e-3, graph: bool = False,
+                     stream=None, bottom_modes: int = 0, sync: bool = True):
+    """Torontonians of a packed batch; returns a list of TorResult when
+    sync is True (else None: the results are in batch.out on the device)."""
+    torch = _torch()
+    B = batch.batch
+    if tiers is None:
+        tptr = None
+    else:
+        if isinstance(tiers, (str, int)):
+            tiers = [tiers] * B
+        t = np.ascontiguousarray([tier_id(x) for x in tiers], dtype=np.int32)
+        tptr = t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    flags = _lib.TOR_FLAG_GRAPH if graph else 0
+    opt = _lib.TorOptionsC(_lib.TOR_ALGO_AUTO, -1, 0, flags, int(bottom_modes))
+    rc = lib().tor_eval_batched(ctypes.c_void_p(batch.O.data_ptr()),
+                                batch.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                batch.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), B, tptr,
+                                float(tau), ctypes.byref(opt), _stream_ptr(stream),
+                                ctypes.c_void_p(batch.out.data_ptr()))
+    check(rc, "tor_eval_batched")
+    if not sync:
+        return None
+    (torch.cuda.current_stream() if stream is None else stream).synchronize()
+    return _results_from(batch.out[:B].cpu().numpy())
+
+
 def tor_debug_level_sums(O, tier="dd", stream=None):
     """(levels, result): levels[m] is L_m = sum over |Z| = m of det^(-1/2),
     each as a Fraction of the returned expansion."""

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <map>
+#include <string>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -33,6 +34,9 @@ struct Workspace {
   tor_result_t* host_res = nullptr;  // pinned
   double* host_lev = nullptr;        // pinned, 4*(TOR_NMAX+1)
   std::map<std::pair<int, int>, ItemTable> tables;  // (n, d) -> prefix items
+  char* meta = nullptr;         // device copy of the batch plan (offsets, indices, tiers)
+  size_t meta_cap = 0;
+  std::map<std::string, hipGraphExec_t> graphs;  // captured batches (TOR_FLAG_GRAPH)
   std::vector<hipEvent_t> evs;  // kernel timing (TOR_FLAG_TIME_KERNEL): start/stop pairs
   int ev_pairs = 0;             // pairs recorded by the last evaluation
   double last_ms = -1.0;
@@ -120,6 +124,9 @@ int ensure_cap(Workspace* w, size_t bytes) {
     w->buf = nullptr;
     w->cap = 0;
   }
+  // captured graphs point into the old buffer
+  for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+  w->graphs.clear();
   TOR_HIP(hipMalloc((void**)&w->buf, ncap));
   w->cap = ncap;
   return TOR_OK;
@@ -265,118 +272,210 @@ int enqueue_tree(Workspace* w, const void* O, int n, int64_t ld, int tier, int m
 }
 
 
-// Right-looking Schur-complement evaluation (MODE_SUM only).
-//   depth 0 -> D_s : breadth-first in HBM, all states kept ("roots")
-//   per chunk      : Cr consecutive roots expanded breadth-first to depth
-//                    D_m = n - s_m, then the middle + bottom kernel over the
-//                    Cr 2^(D_m - D_s) middle states
-// A chunk's last top level is kept near 1.5 GB.
-int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
-                  const tor_options_t* opt, hipStream_t s, RunOut* ro) {
-  int s_m = 0, s_b = 0;
-  schur_levels(tier, n, opt ? opt->bottom_modes : 0, &s_m, &s_b);
-  const int D_m = n - s_m;
-  const size_t rb = schur_value_bytes(tier);
-  const size_t ab = acc_bytes(tier);
-  auto ps = [](int k) { return (size_t)k * (2 * k + 1); };
+// ---------------------------------------------------------------------------
+// Right-looking Schur-complement evaluation of a group of R instances that
+// share n and the tier (MODE_SUM only).
+//   depth 0 -> D_s : breadth-first in HBM over all R roots, every state kept
+//   per chunk      : Cr consecutive depth-D_s states expanded breadth-first to
+//                    depth D_m = n - s_m, then the middle + bottom kernel over
+//                    Cr 2^(D_m - D_s) middle states, their partial sums folded
+//                    per depth-D_s state
+//   end            : partial sums folded per instance; one result each
+// Every fold has a fixed order, so results do not depend on launch shapes.
+// ---------------------------------------------------------------------------
+struct SchurPlan {
+  int tier, n, R, s_m, s_b, D_m, D_s, Dl, Cr, nchunks;
+  size_t Ns, mids, rb, ab;
+  size_t o_rm, o_rg, o_rn, o_m[2], o_g[2], o_n[2], o_part, o_ds, o_inst, o_rsc, o_cnt, o_res;
+  size_t bytes;
+};
+
+size_t psz(int k) { return (size_t)k * (2 * k + 1); }
+
+void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
+  p->tier = tier;
+  p->n = n;
+  p->R = R;
+  schur_levels(tier, n, sb_req, &p->s_m, &p->s_b);
+  p->D_m = n - p->s_m;
+  p->rb = schur_value_bytes(tier);
+  p->ab = acc_bytes(tier);
   // middle states per chunk: about 1.5 GB of them at the last top level
   int LT = 0;
-  while (LT < 22 && ((size_t)2 << LT) * ps(s_m) * rb <= ((size_t)3 << 29)) ++LT;
-  // stage 0 keeps every state of depth D_s; a chunk expands Cr of them
-  int D_s = D_m < 10 ? D_m : 10;
-  if (D_m - D_s > LT) D_s = D_m - LT;
-  const int Dl = D_m - D_s;  // levels expanded per chunk
-  const int lcr = std::min(D_s, LT - Dl);
-  const int Cr = 1 << lcr;             // roots per chunk
-  const int nchunks = 1 << (D_s - lcr);
-  const int D_c = D_s;
+  while (LT < 22 && ((size_t)2 << LT) * psz(p->s_m) * p->rb <= ((size_t)3 << 29)) ++LT;
+  // keep depth D_s (at most 10, at most ~1 GB of states, at least D_m - LT)
+  int D_s = p->D_m < 10 ? p->D_m : 10;
+  while (D_s > 0 && ((size_t)R << D_s) * psz(n - D_s) * p->rb > ((size_t)1 << 30)) --D_s;
+  if (p->D_m - D_s > LT) D_s = p->D_m - LT;
+  p->D_s = D_s;
+  p->Dl = p->D_m - D_s;
+  p->Ns = (size_t)R << D_s;
+  size_t cr = p->Dl >= LT ? 1 : ((size_t)1 << (LT - p->Dl));
+  if (cr > p->Ns) cr = p->Ns;
+  p->Cr = (int)cr;
+  p->nchunks = (int)((p->Ns + cr - 1) / cr);
+  p->mids = cr << p->Dl;
 
-  size_t lvl_vals = ps(n);
-  for (int j = 1; j <= D_s; ++j) lvl_vals = std::max(lvl_vals, ((size_t)1 << j) * ps(n - j));
-  for (int j = 1; j <= Dl; ++j) lvl_vals = std::max(lvl_vals, ((size_t)Cr << j) * ps(n - D_s - j));
-  const size_t lvl_states = std::max((size_t)1 << D_s, (size_t)Cr << Dl);
-  const size_t mids = (size_t)Cr << Dl;
+  size_t lvl_vals = (size_t)R * psz(n);
+  for (int j = 1; j <= D_s; ++j) lvl_vals = std::max(lvl_vals, ((size_t)R << j) * psz(n - j));
+  for (int j = 1; j <= p->Dl; ++j) lvl_vals = std::max(lvl_vals, (cr << j) * psz(n - D_s - j));
+  const size_t lvl_states = std::max(p->Ns, p->mids);
 
   Carver c;
-  const size_t o_rm = c.take(rb * (((size_t)1 << D_s) * ps(n - D_s)));
-  const size_t o_rg = c.take(rb * ((size_t)1 << D_s));
-  const size_t o_rn = c.take(sizeof(int32_t) * ((size_t)1 << D_s));
-  size_t o_m[2], o_g[2], o_n[2];
+  p->o_rm = c.take(p->rb * (p->Ns * psz(n - D_s)));
+  p->o_rg = c.take(p->rb * p->Ns);
+  p->o_rn = c.take(sizeof(int32_t) * p->Ns);
   for (int k = 0; k < 2; ++k) {
-    o_m[k] = c.take(rb * lvl_vals);
-    o_g[k] = c.take(rb * lvl_states);
-    o_n[k] = c.take(sizeof(int32_t) * lvl_states);
+    p->o_m[k] = c.take(p->rb * lvl_vals);
+    p->o_g[k] = c.take(p->rb * lvl_states);
+    p->o_n[k] = c.take(sizeof(int32_t) * lvl_states);
   }
-  const size_t o_part = c.take(ab * 2 * mids);
-  const size_t o_chunk = c.take(ab * 2 * (size_t)nchunks);
-  const size_t o_red = c.take(ab * 2);
-  const size_t o_rsc = c.take(std::max(reduce_scratch_bytes(tier, (int)mids, 2),
-                                       reduce_scratch_bytes(tier, nchunks, 2)));
-  const size_t o_cnt = c.take(sizeof(uint32_t) * 64);
-  const size_t o_res = c.take(sizeof(tor_result_t));
-  TOR_TRY(ensure_cap(w, c.off));
-  char* B = w->buf;
-  uint32_t* cnt = (uint32_t*)(B + o_cnt);
-  int32_t* status = (int32_t*)(cnt + 1);
+  p->o_part = c.take(p->ab * 2 * p->mids);
+  p->o_ds = c.take(p->ab * 2 * p->Ns);
+  p->o_inst = c.take(p->ab * 2 * (size_t)R);
+  p->o_rsc = c.take(reduce_scratch_bytes(tier, (int)std::max(p->mids, p->Ns), 2));
+  p->o_cnt = c.take(sizeof(uint32_t) * 64);
+  p->o_res = c.take(sizeof(tor_result_t));
+  p->bytes = c.off;
+}
 
+// Fold nseg segments of seg_len partials each (a two-stage reduction when one
+// long segment is all there is).
+int fold(int tier, const void* part, int nseg, size_t seg_len, void* out, void* scratch, hipStream_t s) {
+  if (nseg == 1 && seg_len > 4096)
+    return hip_err(launch_reduce_cols(tier, part, (int)seg_len, 2, out, scratch, s));
+  return hip_err(launch_seg_reduce(tier, part, nseg, (int)seg_len, out, s));
+}
+
+// Enqueue a planned group.  O + offs_dev[k] (offs_dev NULL: O itself) is
+// instance k; results go to out[out_index ? out_index[k] : k] (device).
+int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const int64_t* offs_dev,
+                        int64_t ld, const tor_options_t* opt, const int32_t* out_index,
+                        tor_result_t* out, bool timed, hipStream_t s) {
+  const int tier = p.tier, n = p.n;
+  char* B = w->buf;
+  uint32_t* cnt = (uint32_t*)(B + p.o_cnt);
+  int32_t* status = (int32_t*)(cnt + 1);
   int occ = 0;
-  TOR_HIP(leaf_occupancy(tier, s_b, &occ));
+  TOR_HIP(leaf_occupancy(tier, p.s_b, &occ));
   if (occ < 1) return TOR_EUNSUPPORTED;
   int grid = (opt && opt->grid > 0) ? opt->grid : occ * w->cus;
-  if ((size_t)grid > mids) grid = (int)mids;
+  if ((size_t)grid > p.mids) grid = (int)p.mids;
 
   TOR_HIP(launch_zero_words(cnt, 64, s));
-  const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
-  w->ev_pairs = 0;
-  // stage 0: root, then breadth-first to depth D_c into the roots buffer
+  // stage 0: roots, then breadth-first to depth D_s into the kept buffer
   {
     int cur = 0;
-    void* dm = D_c == 0 ? (void*)(B + o_rm) : (void*)(B + o_m[0]);
-    void* dg = D_c == 0 ? (void*)(B + o_rg) : (void*)(B + o_g[0]);
-    int32_t* dn = D_c == 0 ? (int32_t*)(B + o_rn) : (int32_t*)(B + o_n[0]);
-    TOR_HIP(launch_real_root(tier, (const double2*)O, n, ld, dm, dg, dn, s));
-    for (int j = 0; j < D_c; ++j) {
-      const bool last = (j == D_c - 1);
-      void* om = last ? (void*)(B + o_rm) : (void*)(B + o_m[1 - cur]);
-      void* og = last ? (void*)(B + o_rg) : (void*)(B + o_g[1 - cur]);
-      int32_t* on = last ? (int32_t*)(B + o_rn) : (int32_t*)(B + o_n[1 - cur]);
-      TOR_HIP(launch_expand(tier, B + o_m[cur], B + o_g[cur], (const int32_t*)(B + o_n[cur]), n - j,
-                            1 << j, om, og, on, status, s));
+    const bool direct = (p.D_s == 0);
+    void* dm = direct ? (void*)(B + p.o_rm) : (void*)(B + p.o_m[0]);
+    void* dg = direct ? (void*)(B + p.o_rg) : (void*)(B + p.o_g[0]);
+    int32_t* dn = direct ? (int32_t*)(B + p.o_rn) : (int32_t*)(B + p.o_n[0]);
+    TOR_HIP(launch_real_root(tier, (const double2*)O, offs_dev, p.R, n, ld, dm, dg, dn, s));
+    for (int j = 0; j < p.D_s; ++j) {
+      const bool last = (j == p.D_s - 1);
+      void* om = last ? (void*)(B + p.o_rm) : (void*)(B + p.o_m[1 - cur]);
+      void* og = last ? (void*)(B + p.o_rg) : (void*)(B + p.o_g[1 - cur]);
+      int32_t* on = last ? (int32_t*)(B + p.o_rn) : (int32_t*)(B + p.o_n[1 - cur]);
+      TOR_HIP(launch_expand(tier, B + p.o_m[cur], B + p.o_g[cur], (const int32_t*)(B + p.o_n[cur]),
+                            n - j, p.R << j, om, og, on, status, s));
       cur = 1 - cur;
     }
   }
-  // per chunk of Cr roots: expand Dl levels, then the middle + bottom kernel
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const char* im = B + o_rm + rb * ((size_t)ch * Cr * ps(n - D_c));
-    const char* ig = B + o_rg + rb * ((size_t)ch * Cr);
-    const int32_t* in_ = (const int32_t*)(B + o_rn) + (size_t)ch * Cr;
-    int cur = -1;  // -1: the chunk's roots themselves
-    for (int j = 0; j < Dl; ++j) {
+  const size_t rb = p.rb, ab = p.ab;
+  for (int ch = 0; ch < p.nchunks; ++ch) {
+    const size_t first = (size_t)ch * p.Cr;
+    const int cr = (int)std::min<size_t>(p.Cr, p.Ns - first);
+    const char* im = B + p.o_rm + rb * (first * psz(n - p.D_s));
+    const char* ig = B + p.o_rg + rb * first;
+    const int32_t* in_ = (const int32_t*)(B + p.o_rn) + first;
+    int cur = -1;  // -1: the chunk's depth-D_s states themselves
+    for (int j = 0; j < p.Dl; ++j) {
       const int nx = (cur == 0) ? 1 : 0;
-      TOR_HIP(launch_expand(tier, cur < 0 ? (const void*)im : (const void*)(B + o_m[cur]),
-                            cur < 0 ? (const void*)ig : (const void*)(B + o_g[cur]),
-                            cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]), n - D_c - j, Cr << j,
-                            B + o_m[nx], B + o_g[nx], (int32_t*)(B + o_n[nx]), status, s));
+      TOR_HIP(launch_expand(tier, cur < 0 ? (const void*)im : (const void*)(B + p.o_m[cur]),
+                            cur < 0 ? (const void*)ig : (const void*)(B + p.o_g[cur]),
+                            cur < 0 ? in_ : (const int32_t*)(B + p.o_n[cur]), n - p.D_s - j, cr << j,
+                            B + p.o_m[nx], B + p.o_g[nx], (int32_t*)(B + p.o_n[nx]), status, s));
       cur = nx;
     }
-    const void* lm = cur < 0 ? (const void*)im : (const void*)(B + o_m[cur]);
-    const void* lg = cur < 0 ? (const void*)ig : (const void*)(B + o_g[cur]);
-    const int32_t* ln = cur < 0 ? in_ : (const int32_t*)(B + o_n[cur]);
-    if (timed) TOR_TRY(record_ev(w, 2 * ch, s));
-    TOR_HIP(launch_leaf(tier, s_m, s_b, lm, lg, ln, (int)mids, n, B + o_part, status, grid, s));
+    const void* lm = cur < 0 ? (const void*)im : (const void*)(B + p.o_m[cur]);
+    const void* lg = cur < 0 ? (const void*)ig : (const void*)(B + p.o_g[cur]);
+    const int32_t* ln = cur < 0 ? in_ : (const int32_t*)(B + p.o_n[cur]);
+    const int nm = cr << p.Dl;
+    if (timed) TOR_TRY(record_ev(w, 2 * w->ev_pairs, s));
+    TOR_HIP(launch_leaf(tier, p.s_m, p.s_b, lm, lg, ln, nm, n, B + p.o_part, status,
+                        std::min(grid, nm), s));
     if (timed) {
-      TOR_TRY(record_ev(w, 2 * ch + 1, s));
-      w->ev_pairs = ch + 1;
+      TOR_TRY(record_ev(w, 2 * w->ev_pairs + 1, s));
+      w->ev_pairs += 1;
     }
-    TOR_HIP(launch_reduce_cols(tier, B + o_part, (int)mids, 2, B + o_chunk + ab * 2 * ch, B + o_rsc, s));
+    TOR_TRY(fold(tier, B + p.o_part, cr, (size_t)1 << p.Dl, B + p.o_ds + ab * 2 * first, B + p.o_rsc, s));
   }
-  w->last_d = D_m;
-  w->last_grid = grid;
-  TOR_HIP(launch_reduce_cols(tier, B + o_chunk, nchunks, 2, B + o_red, B + o_rsc, s));
+  TOR_TRY(fold(tier, B + p.o_ds, p.R, (size_t)1 << p.D_s, B + p.o_inst, B + p.o_rsc, s));
   const double err_rel = (double)(4 * n * n + n + 8) * unit_roundoff(tier);
-  TOR_HIP(launch_finalize(tier, B + o_red, status, err_rel, (tor_result_t*)(B + o_res), s));
-  ro->dres = (tor_result_t*)(B + o_res);
-  ro->red = B + o_red;
+  TOR_HIP(launch_finalize_batch(tier, B + p.o_inst, p.R, out_index, n, err_rel, out, s));
+  w->last_d = p.D_m;
+  w->last_grid = grid;
+  return TOR_OK;
+}
+
+// Precision selector: fills tier_of[k] for every TOR_AUTO instance with n > 0.
+int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
+                 int batch, double tau, int32_t* tier_of, hipStream_t s) {
+  (void)w; (void)O_packed; (void)offsets; (void)n; (void)batch; (void)tau; (void)tier_of; (void)s;
+  return TOR_EUNSUPPORTED;
+}
+
+// A batch grouped by (n, tier).
+struct BatchGroup {
+  int n, tier;
+  std::vector<int32_t> idx;  // instance indices
+};
+
+int upload_meta(Workspace* w, const void* src, size_t bytes) {
+  if (bytes > w->meta_cap) {
+    if (w->meta) TOR_HIP(hipFree(w->meta));
+    w->meta = nullptr;
+    w->meta_cap = 0;
+    size_t cap = 4096;
+    while (cap < bytes) cap *= 2;
+    TOR_HIP(hipMalloc((void**)&w->meta, cap));
+    w->meta_cap = cap;
+    for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+    w->graphs.clear();
+  }
+  TOR_HIP(hipMemcpy(w->meta, src, bytes, hipMemcpyHostToDevice));
+  return TOR_OK;
+}
+
+// Enqueue every group of a batch (plan already uploaded to w->meta).
+int enqueue_batch(Workspace* w, const std::vector<BatchGroup>& groups,
+                  const std::vector<SchurPlan>& plans, const std::vector<size_t>& meta_off,
+                  size_t triv_off, int ntriv, const void* O_packed, const tor_options_t* opt,
+                  tor_result_t* out, hipStream_t s) {
+  if (ntriv > 0)
+    TOR_HIP(launch_fill_trivial(out, (const int32_t*)(w->meta + triv_off),
+                                (const int32_t*)(w->meta + triv_off) + ntriv, ntriv, s));
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const BatchGroup& g = groups[gi];
+    const int64_t* offs = (const int64_t*)(w->meta + meta_off[gi]);
+    const int32_t* oidx = (const int32_t*)(offs + g.idx.size());
+    TOR_TRY(enqueue_schur_group(w, plans[gi], O_packed, offs, 2 * (int64_t)g.n, opt, oidx, out, false, s));
+  }
+  return TOR_OK;
+}
+
+// Single instance through the Schur path.
+int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
+                  const tor_options_t* opt, hipStream_t s, RunOut* ro) {
+  SchurPlan p;
+  plan_schur(tier, n, 1, opt ? opt->bottom_modes : 0, &p);
+  TOR_TRY(ensure_cap(w, p.bytes));
+  const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
+  w->ev_pairs = 0;
+  tor_result_t* dres = (tor_result_t*)(w->buf + p.o_res);
+  TOR_TRY(enqueue_schur_group(w, p, O, nullptr, ld, opt, nullptr, dres, timed, s));
+  ro->dres = dres;
+  ro->red = w->buf + p.o_inst;
   ro->ncols = 2;
   return TOR_OK;
 }
@@ -420,6 +519,8 @@ int tor_shutdown(void) {
       if (w->host_res) (void)hipHostFree(w->host_res);
       if (w->host_lev) (void)hipHostFree(w->host_lev);
       for (hipEvent_t e : w->evs) (void)hipEventDestroy(e);
+      for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+      if (w->meta) (void)hipFree(w->meta);
       (void)hipSetDevice(cur);
     }
     delete w;
@@ -460,6 +561,123 @@ double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches
   if (grid) *grid = w->last_grid;
   if (launches) *launches = w->last_launches;
   return w->last_ms;
+}
+
+int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
+                     const int32_t* tiers, double tau, const tor_options_t* opt, void* stream,
+                     tor_result_t* out) {
+  if (batch < 0) return TOR_EINVAL;
+  if (batch == 0) return TOR_OK;
+  if (!offsets || !n || !out) return TOR_EINVAL;
+  if (opt && opt->algo != TOR_ALGO_AUTO && opt->algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
+  bool any_work = false;
+  for (int k = 0; k < batch; ++k) {
+    if (n[k] < 0 || n[k] > TOR_NMAX || offsets[k] < 0) return TOR_EINVAL;
+    const int t = tiers ? tiers[k] : TOR_AUTO;
+    if (t != TOR_FP64 && t != TOR_DD && t != TOR_QD && t != TOR_AUTO) return TOR_EINVAL;
+    if (n[k] > 0) any_work = true;
+  }
+  if (any_work && !O_packed) return TOR_EINVAL;
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  // the previous call on this stream may still read the plan buffer
+  TOR_HIP(hipStreamSynchronize(s));
+
+  std::vector<int32_t> tier_of(batch);
+  for (int k = 0; k < batch; ++k) tier_of[k] = tiers ? tiers[k] : TOR_AUTO;
+  bool any_auto = false;
+  for (int k = 0; k < batch; ++k) any_auto = any_auto || (tier_of[k] == TOR_AUTO && n[k] > 0);
+  if (any_auto) TOR_TRY(select_tiers(w, O_packed, offsets, n, batch, tau, tier_of.data(), s));
+
+  const bool use_graph = opt && (opt->flags & TOR_FLAG_GRAPH);
+  std::string key;
+  if (use_graph) {
+    auto put = [&](const void* p, size_t b) { key.append((const char*)p, b); };
+    put(&O_packed, sizeof(O_packed));
+    put(&out, sizeof(out));
+    put(&s, sizeof(s));
+    put(&batch, sizeof(batch));
+    put(offsets, sizeof(int64_t) * batch);
+    put(n, sizeof(int32_t) * batch);
+    put(tier_of.data(), sizeof(int32_t) * batch);
+    if (opt) put(opt, sizeof(*opt));
+    auto it = w->graphs.find(key);
+    if (it != w->graphs.end()) {
+      TOR_HIP(hipGraphLaunch(it->second, s));
+      return TOR_OK;
+    }
+  }
+
+  // group by (n, tier); n = 0 instances are filled directly
+  std::map<std::pair<int, int>, size_t> gmap;
+  std::vector<BatchGroup> groups;
+  std::vector<int32_t> triv_idx, triv_tier;
+  for (int k = 0; k < batch; ++k) {
+    const int t = tier_of[k] == TOR_AUTO ? TOR_DD : tier_of[k];
+    if (n[k] == 0) {
+      triv_idx.push_back(k);
+      triv_tier.push_back(t);
+      continue;
+    }
+    auto key2 = std::make_pair(n[k], t);
+    auto it = gmap.find(key2);
+    if (it == gmap.end()) {
+      gmap[key2] = groups.size();
+      groups.push_back(BatchGroup{n[k], t, {}});
+      it = gmap.find(key2);
+    }
+    groups[it->second].idx.push_back(k);
+  }
+  // plans, one workspace size for all groups (they run one after another)
+  std::vector<SchurPlan> plans(groups.size());
+  size_t need = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    plan_schur(groups[gi].tier, groups[gi].n, (int)groups[gi].idx.size(), opt ? opt->bottom_modes : 0,
+               &plans[gi]);
+    need = std::max(need, plans[gi].bytes);
+  }
+  TOR_TRY(ensure_cap(w, need));
+  // plan buffer: per group offsets (int64) then output indices (int32); trivial list
+  std::vector<char> meta;
+  std::vector<size_t> meta_off(groups.size());
+  auto align8 = [&]() { while (meta.size() % 8) meta.push_back(0); };
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    align8();
+    meta_off[gi] = meta.size();
+    for (int32_t k : groups[gi].idx) {
+      const int64_t o = offsets[k];
+      meta.insert(meta.end(), (const char*)&o, (const char*)&o + 8);
+    }
+    for (int32_t k : groups[gi].idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
+  }
+  align8();
+  const size_t triv_off = meta.size();
+  for (int32_t k : triv_idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
+  for (int32_t t : triv_tier) meta.insert(meta.end(), (const char*)&t, (const char*)&t + 4);
+  if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size()));
+  // the buffer may have moved: nothing captured before this point survives
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    TOR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
+                                 opt, out, s);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc != TOR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    TOR_HIP(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    TOR_HIP(e);
+    w->graphs[key] = exec;
+    TOR_HIP(hipGraphLaunch(exec, s));
+    return TOR_OK;
+  }
+  return enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed, opt,
+                       out, s);
 }
 
 int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,

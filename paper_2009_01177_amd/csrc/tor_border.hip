@@ -367,6 +367,71 @@ __global__ void finalize_kernel(const typename TT::Acc* __restrict__ red,
   *out = r;
 }
 
+template <class TT>
+__global__ __launch_bounds__(256) void seg_reduce_kernel(const typename TT::Acc* __restrict__ part,
+                                                         int seg_len,
+                                                         typename TT::Acc* __restrict__ out) {
+  using Acc = typename TT::Acc;
+  __shared__ Acc bt[256], ba[256];
+  const int sg = blockIdx.x, tid = threadIdx.x;
+  const size_t lo = (size_t)sg * seg_len;
+  Acc t = TT::acc_zero(), a = TT::acc_zero();
+  for (int i = tid; i < seg_len; i += 256) {
+    t = TT::acc_merge(t, part[(lo + i) * 2]);
+    a = TT::acc_merge(a, part[(lo + i) * 2 + 1]);
+  }
+  bt[tid] = t;
+  ba[tid] = a;
+  __syncthreads();
+  for (int s = 128; s >= 1; s >>= 1) {
+    if (tid < s) {
+      bt[tid] = TT::acc_merge(bt[tid], bt[tid + s]);
+      ba[tid] = TT::acc_merge(ba[tid], ba[tid + s]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    out[(size_t)sg * 2] = bt[0];
+    out[(size_t)sg * 2 + 1] = ba[0];
+  }
+}
+
+__device__ inline bool acc_finite(const dd& a) { return isfinite(a.hi) && isfinite(a.lo); }
+__device__ inline bool acc_finite(const qd& a) {
+  return isfinite(a.x[0]) && isfinite(a.x[1]) && isfinite(a.x[2]) && isfinite(a.x[3]);
+}
+
+template <class TT>
+__global__ void finalize_batch_kernel(const typename TT::Acc* __restrict__ red, int ninst,
+                                      const int32_t* __restrict__ out_index, double err_rel,
+                                      tor_result_t* __restrict__ out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ninst) return;
+  tor_result_t r;
+  acc_store(red[2 * k], r.tor);
+  acc_store2(red[2 * k + 1], r.abs_sum);
+  r.err_bound = err_rel * r.abs_sum[0];
+  r.tier_used = TT::id;
+  r.status = (acc_finite(red[2 * k]) && acc_finite(red[2 * k + 1])) ? TOR_OK : TOR_ENOTPD;
+  out[out_index ? out_index[k] : k] = r;
+}
+
+__global__ void fill_trivial_kernel(tor_result_t* __restrict__ out,
+                                    const int32_t* __restrict__ idx,
+                                    const int32_t* __restrict__ tiers, int count) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= count) return;
+  tor_result_t r;
+  for (int i = 0; i < 4; ++i) r.tor[i] = 0.0;
+  r.tor[0] = 1.0;
+  r.abs_sum[0] = 1.0;
+  r.abs_sum[1] = 0.0;
+  r.err_bound = 0.0;
+  r.tier_used = tiers[k];
+  r.status = TOR_OK;
+  out[idx[k]] = r;
+}
+
 template <class Acc>
 __global__ void expand_terms_kernel(const Acc* __restrict__ part, int nitems, double* __restrict__ out4) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -488,6 +553,47 @@ hipError_t launch_finalize(int tier, const void* red, const int32_t* status, dou
       hipLaunchKernelGGL(finalize_kernel<TierQD>, dim3(1), dim3(64), 0, s, (const qd*)red, status,
                          err_rel, out);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_reduce(int tier, const void* part, int nseg, int seg_len, void* out,
+                             hipStream_t s) {
+  if (nseg <= 0) return hipSuccess;
+  if (tier == TOR_QD)
+    hipLaunchKernelGGL(seg_reduce_kernel<TierQD>, dim3(nseg), dim3(256), 0, s, (const qd*)part,
+                       seg_len, (qd*)out);
+  else
+    hipLaunchKernelGGL(seg_reduce_kernel<TierDD>, dim3(nseg), dim3(256), 0, s, (const dd*)part,
+                       seg_len, (dd*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(int tier, const void* red, int ninst, const int32_t* out_index,
+                                 int n, double err_rel, tor_result_t* out, hipStream_t s) {
+  (void)n;
+  if (ninst <= 0) return hipSuccess;
+  const dim3 g((ninst + 63) / 64), b(64);
+  switch (tier) {
+    case TOR_FP64:
+      hipLaunchKernelGGL(finalize_batch_kernel<TierF64>, g, b, 0, s, (const dd*)red, ninst,
+                         out_index, err_rel, out);
+      break;
+    case TOR_DD:
+      hipLaunchKernelGGL(finalize_batch_kernel<TierDD>, g, b, 0, s, (const dd*)red, ninst,
+                         out_index, err_rel, out);
+      break;
+    default:
+      hipLaunchKernelGGL(finalize_batch_kernel<TierQD>, g, b, 0, s, (const qd*)red, ninst,
+                         out_index, err_rel, out);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_trivial(tor_result_t* out, const int32_t* idx, const int32_t* tiers,
+                               int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_trivial_kernel, dim3((count + 63) / 64), dim3(64), 0, s, out, idx, tiers,
+                     count);
   return hipGetLastError();
 }
 

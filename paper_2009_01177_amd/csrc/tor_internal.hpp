@@ -49,6 +49,20 @@ size_t reduce_scratch_bytes(int tier, int nitems, int ncols);
 hipError_t launch_reduce_cols(int tier, const void* partials, int nitems, int ncols, void* red,
                               void* scratch, hipStream_t s);
 
+// Fixed-order sums of nseg contiguous segments of seg_len items of
+// part[][2] into out[nseg][2].
+hipError_t launch_seg_reduce(int tier, const void* part, int nseg, int seg_len, void* out,
+                             hipStream_t s);
+
+// One tor_result_t per instance from red[ninst][2]; an instance whose sums
+// are not finite (a pivot was not > 0) gets status TOR_ENOTPD.
+hipError_t launch_finalize_batch(int tier, const void* red, int ninst, const int32_t* out_index,
+                                 int n, double err_rel, tor_result_t* out, hipStream_t s);
+
+// out[idx[k]] = the n = 0 result (Tor = 1) with tier tiers[k], k < count.
+hipError_t launch_fill_trivial(tor_result_t* out, const int32_t* idx, const int32_t* tiers,
+                               int count, hipStream_t s);
+
 // Build the tor_result_t from the two reduced columns (signed sum, |sum|).
 hipError_t launch_finalize(int tier, const void* red, const int32_t* status, double err_rel,
                            tor_result_t* out, hipStream_t s);
@@ -61,8 +75,10 @@ hipError_t launch_expand_terms(int tier, const void* partials, int nitems, doubl
 size_t schur_value_bytes(int tier);
 // middle-level (s_m) and bottom-level (s_b) mode counts for a tier and n
 void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b);
-hipError_t launch_real_root(int tier, const double2* O, int n, int64_t ld, void* mat, void* g,
-                            int32_t* m, hipStream_t s);
+// Root states of ninst instances of n modes: instance k's O starts at
+// O + offs[k] (offs NULL: one instance at O), leading dimension ld.
+hipError_t launch_real_root(int tier, const double2* O, const int64_t* offs, int ninst, int n,
+                            int64_t ld, void* mat, void* g, int32_t* m, hipStream_t s);
 hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
                          int s, int nst, void* out_mat, void* out_g, int32_t* out_m,
                          int32_t* status, hipStream_t st);

@@ -164,10 +164,13 @@ struct Bottom {
 // --------------------------------------------------------------------------
 
 template <class TT>
-__global__ void real_root_kernel(const double2* __restrict__ O, int n, int64_t ld,
-                                 typename TT::R* __restrict__ mat, typename TT::R* __restrict__ g,
-                                 int32_t* __restrict__ msz) {
+__global__ void real_root_kernel(const double2* __restrict__ O, const int64_t* __restrict__ offs,
+                                 int n, int64_t ld, typename TT::R* __restrict__ mat,
+                                 typename TT::R* __restrict__ g, int32_t* __restrict__ msz) {
   using R = typename TT::R;
+  const int inst = blockIdx.y;  // instance within the group
+  const double2* Oi = O + (offs ? offs[inst] : 0);
+  R* out = mat + (size_t)inst * psize(n);
   const int total = psize(n);
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
     // e -> (r, c), r >= c
@@ -180,24 +183,24 @@ __global__ void real_root_kernel(const double2* __restrict__ O, int n, int64_t l
     // O00_ij and O01_ij from the lower triangle of O (block order)
     double2 x;  // O00_ij
     if (i >= j) {
-      x = O[(int64_t)i * ld + j];
+      x = Oi[(int64_t)i * ld + j];
     } else {
-      const double2 w = O[(int64_t)j * ld + i];
+      const double2 w = Oi[(int64_t)j * ld + i];
       x = make_double2(w.x, -w.y);
     }
-    const double2 w1 = O[(int64_t)(j + n) * ld + i];  // O10_ji = conj(O01_ij)
-    const double2 y = make_double2(w1.x, -w1.y);      // O01_ij
+    const double2 w1 = Oi[(int64_t)(j + n) * ld + i];  // O10_ji = conj(O01_ij)
+    const double2 y = make_double2(w1.x, -w1.y);       // O01_ij
     const double dlt = (i == j && qi == qj) ? 1.0 : 0.0;
     R v;
     if (qi == 0 && qj == 0) v = r_from_sum<R>(dlt, -x.x, -y.x);       // delta - Re(O00 + O01)
     else if (qi == 0 && qj == 1) v = r_from_sum<R>(0.0, x.y, -y.y);   // Im(O00 - O01)
     else if (qi == 1 && qj == 0) v = r_from_sum<R>(0.0, -x.y, -y.y);  // -Im(O00 + O01)
     else v = r_from_sum<R>(dlt, -x.x, y.x);                           // delta - Re(O00 - O01)
-    mat[e] = v;
+    out[e] = v;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    g[0] = r_of<R>(1.0);
-    msz[0] = 0;
+    g[inst] = r_of<R>(1.0);
+    msz[inst] = 0;
   }
 }
 
@@ -463,20 +466,22 @@ void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b) {
   *s_b = sb;
 }
 
-hipError_t launch_real_root(int tier, const double2* O, int n, int64_t ld, void* mat, void* g,
-                            int32_t* m, hipStream_t s) {
+hipError_t launch_real_root(int tier, const double2* O, const int64_t* offs, int ninst, int n,
+                            int64_t ld, void* mat, void* g, int32_t* m, hipStream_t s) {
   const int total = psize(n);
-  const dim3 grid((total + 255) / 256), block(256);
+  const dim3 grid((total + 255) / 256, ninst), block(256);
   switch (tier) {
     case TOR_FP64:
-      hipLaunchKernelGGL(real_root_kernel<TierF64>, grid, block, 0, s, O, n, ld, (double*)mat,
+      hipLaunchKernelGGL(real_root_kernel<TierF64>, grid, block, 0, s, O, offs, n, ld, (double*)mat,
                          (double*)g, m);
       break;
     case TOR_DD:
-      hipLaunchKernelGGL(real_root_kernel<TierDD>, grid, block, 0, s, O, n, ld, (dd*)mat, (dd*)g, m);
+      hipLaunchKernelGGL(real_root_kernel<TierDD>, grid, block, 0, s, O, offs, n, ld, (dd*)mat,
+                         (dd*)g, m);
       break;
     default:
-      hipLaunchKernelGGL(real_root_kernel<TierQD>, grid, block, 0, s, O, n, ld, (qd*)mat, (qd*)g, m);
+      hipLaunchKernelGGL(real_root_kernel<TierQD>, grid, block, 0, s, O, offs, n, ld, (qd*)mat,
+                         (qd*)g, m);
   }
   return hipGetLastError();
 }

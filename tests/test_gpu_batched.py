@@ -1,0 +1,86 @@
+"""Batched path (many instances of uneven n, one launch sequence, optional
+HIP graph) against the float128 oracle and against single evaluations."""
+import numpy as np
+import pytest
+
+import gbs_inputs as g
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "dd": 1e-25, "qd": 1e-30}
+
+
+@pytest.fixture(scope="module")
+def tor():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_01177_amd as t
+    t.tor_init()
+    return t
+
+
+def _mixed(count, nlo, nhi, seed):
+    rng = np.random.default_rng(seed)
+    Os = []
+    for i in range(count):
+        n = int(rng.integers(nlo, nhi + 1))
+        Os.append(g.random_instance(n, seed * 1000 + i) if n > 0 else np.zeros((0, 0), np.complex128))
+    return Os
+
+
+@pytest.mark.parametrize("tier", ["fp64", "dd", "qd"])
+def test_batch_matches_oracle(tor, tier):
+    Os = _mixed(40, 0, 13, 7)
+    print(f"[batched] tier={tier} ns={[o.shape[0] // 2 for o in Os]}", flush=True)
+    b = tor.Batch(Os)
+    res = tor.tor_eval_batched(b, tiers=tier)
+    for O, r in zip(Os, res):
+        ref = oracle.tor(O)
+        assert r.status == 0
+        assert float(abs(r.exact - ref["tor"]) / ref["abs_sum"]) <= TOL[tier]
+
+
+def test_batch_mixed_tiers_and_single_agreement(tor):
+    Os = _mixed(30, 1, 18, 11)
+    tiers = ["fp64", "dd", "qd"] * 10
+    b = tor.Batch(Os)
+    res = tor.tor_eval_batched(b, tiers=tiers)
+    for O, t, r in zip(Os, tiers, res):
+        one = tor.tor_eval(O, tier=t, algo="schur")
+        assert r.tier_used == one.tier_used
+        assert float(abs(r.exact - one.exact) / one.abs_exact) <= TOL[t]
+
+
+def test_graph_replay_is_bitwise_identical(tor):
+    import torch
+    Os = _mixed(64, 4, 16, 3)
+    b = tor.Batch(Os)
+    eager = tor.tor_eval_batched(b, tiers="dd")
+    for rep in range(3):
+        b.out.zero_()
+        # unrelated eager work on the same stream between replays
+        x = torch.randn(1000, device="cuda").sum().item()
+        got = tor.tor_eval_batched(b, tiers="dd", graph=True)
+        assert [r.expansion for r in got] == [r.expansion for r in eager], rep
+        assert np.isfinite(x)
+
+
+def test_not_positive_definite_instance_is_flagged(tor):
+    Os = _mixed(6, 3, 6, 5)
+    Os[2] = (2.0 * np.eye(8)).astype(np.complex128)
+    b = tor.Batch(Os)
+    res = tor.tor_eval_batched(b, tiers="dd")
+    assert [r.status for r in res] == [0, 0, -2, 0, 0, 0]
+
+
+def test_config3_like_batch(tor):
+    """The batched workload's generator (one 100-mode lossy state, uneven
+    click patterns), cut to 96 instances of n <= 14 for the oracle."""
+    Os = [O for O in g.batched_workload(batch=400) if O.shape[0] // 2 <= 14][:96]
+    b = tor.Batch(Os)
+    res = tor.tor_eval_batched(b, tiers="dd", graph=True)
+    for O, r in zip(Os, res):
+        ref = oracle.tor(O)
+        assert float(abs(r.exact - ref["tor"]) / ref["abs_sum"]) <= 1e-25
