@@ -37,6 +37,7 @@ struct Workspace {
   char* meta = nullptr;         // device copy of the batch plan (offsets, indices, tiers)
   size_t meta_cap = 0;
   std::map<std::string, hipGraphExec_t> graphs;  // captured batches (TOR_FLAG_GRAPH)
+  hipStream_t cap_stream = nullptr;              // private stream graphs are captured on
   std::vector<hipEvent_t> evs;  // kernel timing (TOR_FLAG_TIME_KERNEL): start/stop pairs
   int ev_pairs = 0;             // pairs recorded by the last evaluation
   double last_ms = -1.0;
@@ -521,6 +522,7 @@ int tor_shutdown(void) {
       for (hipEvent_t e : w->evs) (void)hipEventDestroy(e);
       for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
       if (w->meta) (void)hipFree(w->meta);
+      if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
       (void)hipSetDevice(cur);
     }
     delete w;
@@ -658,11 +660,15 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size()));
   // the buffer may have moved: nothing captured before this point survives
   if (use_graph) {
+    // capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured), replay on the caller's
+    if (!w->cap_stream) TOR_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = w->cap_stream;
     hipGraph_t graph = nullptr;
-    TOR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    TOR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     const int rc = enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
-                                 opt, out, s);
-    hipError_t e = hipStreamEndCapture(s, &graph);
+                                 opt, out, cs);
+    hipError_t e = hipStreamEndCapture(cs, &graph);
     if (rc != TOR_OK) {
       if (graph) (void)hipGraphDestroy(graph);
       return rc;
