@@ -38,7 +38,8 @@ class TorResult:
     value: float = field(init=False)
 
     def __post_init__(self):
-        self.value = float(sum(Fraction(x) for x in self.expansion))
+        finite = all(np.isfinite(self.expansion))
+        self.value = float(sum(Fraction(x) for x in self.expansion)) if finite else float("nan")
 
     @property
     def exact(self) -> Fraction:
