@@ -149,7 +149,12 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
  *   out       device, batch results; status TOR_ENOTPD marks an instance
  *             whose I - O is not positive definite
  * The call waits for `stream` to drain, uploads the batch plan, then
- * enqueues the evaluation and returns without waiting for it. */
+ * enqueues the evaluation and returns without waiting for it.  With
+ * TOR_AUTO instances it is synchronous: the tiers are chosen first, and a
+ * sample of the instances given FP64 or DD (1/32 of each, at least one;
+ * TOR_SPOT_FRACTION overrides) is re-evaluated one tier up; when a sample
+ * misses tau, every instance of that tier predicted at least as hard is
+ * re-evaluated one tier up (tor_last_select_stats reports the counts). */
 int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
                      const int32_t* tiers, double tau, const tor_options_t* opt, void* stream,
                      tor_result_t* out);
@@ -178,6 +183,91 @@ int tor_debug_sampled_terms(const void* O, int32_t n, int64_t ld, int32_t tier,
  * the split depth (border) or the middle-level depth n - s_m (Schur),
  * *grid the workgroups per launch.  Any pointer may be NULL.  -1 if none. */
 double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches);
+
+/* ---- Precision selector (TOR_AUTO) --------------------------------------
+ * The paper picks its precision once per run from bounds on the largest and
+ * smallest intermediate values (Sec. 5.4, Eq. 5-7).  Here a small network
+ * predicts each instance's cancellation ratio kappa = S_abs / |Tor| from
+ * cheap features and picks the cheapest tier expected to meet the accuracy
+ * target; outside the network's training range the bound estimate decides. */
+
+#define TOR_NFEAT 12      /* features per instance (see tor_features) */
+#define TOR_MLP_H1 32     /* network: TOR_NFEAT -> 32 -> 32 -> 1, tanh hidden */
+#define TOR_MLP_H2 32
+#define TOR_MLP_PARAMS 1505
+
+/* Features of `batch` instances (all n >= 1), binary64, on the device:
+ *   f0 n; f1 -1/2 log det(I-O); f2 sum_k log((1+q_k)/(1-q_k)) with
+ *   q_k = det(I-O)_{kk}^(1/2); f3 mean_k -log q_k; f4 a = mean Re O_kk;
+ *   f5 k = ((1-a)^2 - det(I-O)^(1/n))/n; f6 sum_{i<j} log(det_ij/(det_i det_j));
+ *   f7 max q_k; f8 min q_k; f9, f10 log of the smallest and largest
+ *   Cholesky pivot of I-O in quadrature form; f11 log mean_{i<j} det_ij^(-1/2).
+ * Inputs as tor_eval_batched (offsets, n on the host); feats device,
+ * batch x TOR_NFEAT.  Enqueued on `stream`. */
+int tor_features(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
+                 void* stream, double* feats);
+
+/* Network forward pass: Y[b] = net(theta; (X[b] - mean) / std).  All device
+ * pointers; X is B x TOR_NFEAT.  Enqueued on `stream`. */
+int tor_mlp_forward(const double* theta, const double* mean, const double* std, const double* X,
+                    int32_t B, void* stream, double* Y);
+
+/* Gradient of the mean asymmetric squared loss
+ *   L = (1/B) sum_b w_b (y_b - net(x_b))^2,  w_b = under if y_b > net(x_b) else over
+ * (under > over penalises under-predicting kappa).  grad: device,
+ * TOR_MLP_PARAMS; loss: device, 1 (or NULL).  Per-sample gradients are
+ * summed in sample order.  Enqueued on `stream`. */
+int tor_mlp_grad(const double* theta, const double* mean, const double* std, const double* X,
+                 const double* y, int32_t B, double under, double over, void* stream, double* grad,
+                 double* loss);
+
+/* One Adam step (moments m, v, step >= 1) on theta in place; device. */
+int tor_mlp_adam(double* theta, const double* grad, double* m, double* v, double lr, double beta1,
+                 double beta2, double eps, int32_t step, void* stream);
+
+/* The selector used by TOR_AUTO (one per process). */
+typedef struct tor_selector {
+  double theta[TOR_MLP_PARAMS];
+  double mean[TOR_NFEAT], std[TOR_NFEAT]; /* input standardisation */
+  double fmin[TOR_NFEAT], fmax[TOR_NFEAT]; /* training range; outside it the
+                                              bound estimate decides */
+  double log10_c[3]; /* per tier: log10 C_t in |dTor|/|Tor| <= C_t kappa u_t,
+                        calibrated on training data */
+  double margin;     /* extra log10 safety margin on the prediction */
+  int32_t nmin, nmax; /* training range of n */
+  int32_t trained;    /* 0: no network, the bound estimate decides */
+  int32_t reserved;
+} tor_selector_t;
+
+int tor_selector_set(const tor_selector_t* sel); /* NULL clears it */
+int tor_selector_get(tor_selector_t* sel);
+int tor_selector_save(const char* path);
+int tor_selector_load(const char* path);
+
+/* Bound-based estimate of the significand bits an instance needs (Eq. 7 read
+ * for floating tiers): log2 of the rigorous S_abs <= 2^n det(I-O)^(-1/2) over
+ * the Eq. 6 estimate of |Tor| (with a and k of Eq. 5), plus log2(1/tau)
+ * (the wanted digits) and log2(0.5 2^n n^2) (accumulated error).  feats:
+ * host, one instance's TOR_NFEAT features.  No GPU needed. */
+double tor_fallback_bits(const double* feats, double tau);
+
+/* Tiers TOR_AUTO would pick for each instance, without evaluating them.
+ *   tiers, log10_kappa, source: host, batch entries each (the last two may
+ *   be NULL); source[k] = 0 network, 1 bound estimate.  Synchronous. */
+int tor_select_tiers(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
+                     double tau, void* stream, int32_t* tiers, double* log10_kappa,
+                     int32_t* source);
+
+/* What the last TOR_AUTO batch did. */
+typedef struct tor_select_stats {
+  int32_t n_fp64, n_dd, n_qd;  /* tiers chosen */
+  int32_t n_fallback;          /* decided by the bound estimate */
+  int32_t n_spot;              /* re-evaluated at the next tier as a check */
+  int32_t n_violations;        /* spot checks that missed tau */
+  int32_t n_escalated;         /* instances moved up a tier afterwards */
+  int32_t reserved;
+} tor_select_stats_t;
+int tor_last_select_stats(tor_select_stats_t* out);
 
 /* ---- Host-side scheduling helpers (no GPU needed) ----------------------
  * Alg. 2's mask functions, used to order the work items by subset size. */

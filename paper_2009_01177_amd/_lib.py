@@ -24,7 +24,13 @@ EXPORTS = (
     "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval", "tor_eval_batched",
     "tor_debug_level_sums", "tor_debug_sampled_terms", "tor_last_kernel_ms",
     "tor_next_mask", "tor_kth_mask", "tor_plan_items",
+    "tor_features", "tor_mlp_forward", "tor_mlp_grad", "tor_mlp_adam",
+    "tor_selector_set", "tor_selector_get", "tor_selector_save", "tor_selector_load",
+    "tor_fallback_bits", "tor_select_tiers", "tor_last_select_stats",
 )
+
+TOR_NFEAT = 12
+TOR_MLP_PARAMS = 1505
 
 
 class TorResultC(ctypes.Structure):
@@ -46,6 +52,28 @@ class TorOptionsC(ctypes.Structure):
         ("bottom_modes", ctypes.c_int32),
         ("reserved", ctypes.c_int32 * 3),
     ]
+
+
+class TorSelectorC(ctypes.Structure):
+    _fields_ = [
+        ("theta", ctypes.c_double * 1505),
+        ("mean", ctypes.c_double * 12),
+        ("std", ctypes.c_double * 12),
+        ("fmin", ctypes.c_double * 12),
+        ("fmax", ctypes.c_double * 12),
+        ("log10_c", ctypes.c_double * 3),
+        ("margin", ctypes.c_double),
+        ("nmin", ctypes.c_int32),
+        ("nmax", ctypes.c_int32),
+        ("trained", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class TorSelectStatsC(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in
+                ("n_fp64", "n_dd", "n_qd", "n_fallback", "n_spot", "n_violations", "n_escalated",
+                 "reserved")]
 
 
 class TorError(RuntimeError):
@@ -95,6 +123,31 @@ def lib():
     L.tor_debug_sampled_terms.argtypes = [vp, i32, i64, i32, vp, i64, vp, vp]
     L.tor_last_kernel_ms.restype = ctypes.c_double
     L.tor_last_kernel_ms.argtypes = [ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    pd = ctypes.POINTER(ctypes.c_double)
+    L.tor_features.restype = ctypes.c_int
+    L.tor_features.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), i32, vp, vp]
+    L.tor_mlp_forward.restype = ctypes.c_int
+    L.tor_mlp_forward.argtypes = [vp, vp, vp, vp, i32, vp, vp]
+    L.tor_mlp_grad.restype = ctypes.c_int
+    L.tor_mlp_grad.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    L.tor_mlp_adam.restype = ctypes.c_int
+    L.tor_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, i32, vp]
+    L.tor_selector_set.restype = ctypes.c_int
+    L.tor_selector_set.argtypes = [ctypes.POINTER(TorSelectorC)]
+    L.tor_selector_get.restype = ctypes.c_int
+    L.tor_selector_get.argtypes = [ctypes.POINTER(TorSelectorC)]
+    L.tor_selector_save.restype = ctypes.c_int
+    L.tor_selector_save.argtypes = [ctypes.c_char_p]
+    L.tor_selector_load.restype = ctypes.c_int
+    L.tor_selector_load.argtypes = [ctypes.c_char_p]
+    L.tor_fallback_bits.restype = ctypes.c_double
+    L.tor_fallback_bits.argtypes = [pd, ctypes.c_double]
+    L.tor_select_tiers.restype = ctypes.c_int
+    L.tor_select_tiers.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), i32, ctypes.c_double, vp,
+                                   ctypes.POINTER(i32), pd, ctypes.POINTER(i32)]
+    L.tor_last_select_stats.restype = ctypes.c_int
+    L.tor_last_select_stats.argtypes = [ctypes.POINTER(TorSelectStatsC)]
     L.tor_next_mask.restype = u64
     L.tor_next_mask.argtypes = [u64]
     L.tor_kth_mask.restype = u64

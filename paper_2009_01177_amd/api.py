@@ -174,6 +174,94 @@ def tor_eval_batched(batch: "Batch", tiers=None, tau: float = 1e-3, graph: bool 
     return _results_from(batch.out[:B].cpu().numpy())
 
 
+# ---- precision selector ----------------------------------------------------
+
+def _dptr_t(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def tor_features(batch: "Batch", stream=None):
+    """(B, 12) float64 device tensor of the instances' selector features."""
+    torch = _torch()
+    f = torch.zeros((batch.batch, _lib.TOR_NFEAT), dtype=torch.float64, device=batch.O.device)
+    rc = lib().tor_features(_dptr_t(batch.O),
+                            batch.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                            batch.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), batch.batch,
+                            _stream_ptr(stream), _dptr_t(f))
+    check(rc, "tor_features")
+    return f
+
+
+def tor_mlp_forward(theta, mean, std, X, stream=None):
+    torch = _torch()
+    Y = torch.zeros(X.shape[0], dtype=torch.float64, device=X.device)
+    check(lib().tor_mlp_forward(_dptr_t(theta), _dptr_t(mean), _dptr_t(std), _dptr_t(X), X.shape[0],
+                                _stream_ptr(stream), _dptr_t(Y)), "tor_mlp_forward")
+    return Y
+
+
+def tor_mlp_grad(theta, mean, std, X, y, under=4.0, over=1.0, stream=None):
+    """(grad, loss) device tensors."""
+    torch = _torch()
+    grad = torch.zeros(_lib.TOR_MLP_PARAMS, dtype=torch.float64, device=X.device)
+    loss = torch.zeros(1, dtype=torch.float64, device=X.device)
+    check(lib().tor_mlp_grad(_dptr_t(theta), _dptr_t(mean), _dptr_t(std), _dptr_t(X), _dptr_t(y),
+                             X.shape[0], float(under), float(over), _stream_ptr(stream), _dptr_t(grad),
+                             _dptr_t(loss)), "tor_mlp_grad")
+    return grad, loss
+
+
+def tor_mlp_adam(theta, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    check(lib().tor_mlp_adam(_dptr_t(theta), _dptr_t(grad), _dptr_t(m), _dptr_t(v), float(lr),
+                             float(beta1), float(beta2), float(eps), int(step), _stream_ptr(stream)),
+          "tor_mlp_adam")
+
+
+def tor_selector_set(sel: "_lib.TorSelectorC | None"):
+    check(lib().tor_selector_set(ctypes.byref(sel) if sel is not None else None), "tor_selector_set")
+
+
+def tor_selector_get() -> "_lib.TorSelectorC":
+    sel = _lib.TorSelectorC()
+    check(lib().tor_selector_get(ctypes.byref(sel)), "tor_selector_get")
+    return sel
+
+
+def tor_selector_save(path: str):
+    check(lib().tor_selector_save(str(path).encode()), "tor_selector_save")
+
+
+def tor_selector_load(path: str):
+    check(lib().tor_selector_load(str(path).encode()), "tor_selector_load")
+
+
+def tor_fallback_bits(feats, tau: float) -> float:
+    f = np.ascontiguousarray(np.asarray(feats, dtype=np.float64))
+    return float(lib().tor_fallback_bits(f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tau)))
+
+
+def tor_select_tiers(batch: "Batch", tau: float, stream=None):
+    """(tiers, log10_kappa_pred, source) per instance (numpy)."""
+    B = batch.batch
+    t = np.zeros(B, dtype=np.int32)
+    k = np.zeros(B, dtype=np.float64)
+    src = np.zeros(B, dtype=np.int32)
+    rc = lib().tor_select_tiers(_dptr_t(batch.O),
+                                batch.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                batch.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), B, float(tau),
+                                _stream_ptr(stream), t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                k.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                src.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    check(rc, "tor_select_tiers")
+    return t, k, src
+
+
+def tor_last_select_stats() -> dict:
+    st = _lib.TorSelectStatsC()
+    check(lib().tor_last_select_stats(ctypes.byref(st)), "tor_last_select_stats")
+    return {name: int(getattr(st, name)) for name, _ in st._fields_ if name != "reserved"}
+
+
 def tor_debug_level_sums(O, tier="dd", stream=None):
     """(levels, result): levels[m] is L_m = sum over |Z| = m of det^(-1/2),
     each as a Fraction of the returned expansion."""

@@ -3,6 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+
+#include <cmath>
 #include <stdint.h>
 #include <string.h>
 
@@ -38,6 +42,8 @@ struct Workspace {
   size_t meta_cap = 0;
   std::map<std::string, hipGraphExec_t> graphs;  // captured batches (TOR_FLAG_GRAPH)
   hipStream_t cap_stream = nullptr;              // private stream graphs are captured on
+  char* aux = nullptr;                           // selector scratch
+  size_t aux_cap = 0;
   std::vector<hipEvent_t> evs;  // kernel timing (TOR_FLAG_TIME_KERNEL): start/stop pairs
   int ev_pairs = 0;             // pairs recorded by the last evaluation
   double last_ms = -1.0;
@@ -46,6 +52,11 @@ struct Workspace {
 
 std::mutex g_mu;
 std::map<int, Workspace*> g_ws;
+
+std::mutex g_sel_mu;
+tor_selector_t g_sel;  // zero-initialised: no network
+int g_sel_version = 0;
+tor_select_stats_t g_stats;
 
 inline int hip_err(hipError_t e) { return e == hipSuccess ? TOR_OK : (e == hipErrorOutOfMemory ? TOR_ENOMEM : TOR_EHIP); }
 
@@ -419,13 +430,6 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
   return TOR_OK;
 }
 
-// Precision selector: fills tier_of[k] for every TOR_AUTO instance with n > 0.
-int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
-                 int batch, double tau, int32_t* tier_of, hipStream_t s) {
-  (void)w; (void)O_packed; (void)offsets; (void)n; (void)batch; (void)tau; (void)tier_of; (void)s;
-  return TOR_EUNSUPPORTED;
-}
-
 // A batch grouped by (n, tier).
 struct BatchGroup {
   int n, tier;
@@ -462,6 +466,308 @@ int enqueue_batch(Workspace* w, const std::vector<BatchGroup>& groups,
     const int32_t* oidx = (const int32_t*)(offs + g.idx.size());
     TOR_TRY(enqueue_schur_group(w, plans[gi], O_packed, offs, 2 * (int64_t)g.n, opt, oidx, out, false, s));
   }
+  return TOR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+// Scratch device memory for the selector (features, predictions, gradients),
+// separate from the evaluation workspace so either may grow independently.
+int ensure_aux(Workspace* w, size_t bytes, hipStream_t s) {
+  if (bytes <= w->aux_cap) return TOR_OK;
+  TOR_HIP(hipStreamSynchronize(s));
+  TOR_HIP(hipDeviceSynchronize());
+  if (w->aux) TOR_HIP(hipFree(w->aux));
+  w->aux = nullptr;
+  w->aux_cap = 0;
+  size_t cap = 1 << 20;
+  while (cap < bytes) cap *= 2;
+  TOR_HIP(hipMalloc((void**)&w->aux, cap));
+  w->aux_cap = cap;
+  return TOR_OK;
+}
+
+// Evaluate the instances idx (indices into the batch arrays) at the tiers
+// tier_of[k] (no TOR_AUTO left), results to out[k].
+int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
+               const std::vector<int32_t>& idx, const std::vector<int32_t>& tier_of,
+               const tor_options_t* opt, tor_result_t* out, bool use_graph, hipStream_t s) {
+  std::string key;
+  if (use_graph) {
+    auto put = [&](const void* p, size_t b) { key.append((const char*)p, b); };
+    put(&O_packed, sizeof(O_packed));
+    put(&out, sizeof(out));
+    put(&s, sizeof(s));
+    for (int32_t k : idx) {
+      put(&k, 4);
+      put(offsets + k, 8);
+      put(n + k, 4);
+      put(&tier_of[k], 4);
+    }
+    if (opt) put(opt, sizeof(*opt));
+    auto it = w->graphs.find(key);
+    if (it != w->graphs.end()) {
+      TOR_HIP(hipGraphLaunch(it->second, s));
+      return TOR_OK;
+    }
+  }
+  // group by (n, tier); n = 0 instances are filled directly
+  std::map<std::pair<int, int>, size_t> gmap;
+  std::vector<BatchGroup> groups;
+  std::vector<int32_t> triv_idx, triv_tier;
+  for (int32_t k : idx) {
+    const int t = tier_of[k];
+    if (n[k] == 0) {
+      triv_idx.push_back(k);
+      triv_tier.push_back(t == TOR_AUTO ? TOR_FP64 : t);
+      continue;
+    }
+    if (t != TOR_FP64 && t != TOR_DD && t != TOR_QD) return TOR_EINVAL;
+    auto key2 = std::make_pair((int)n[k], t);
+    auto it = gmap.find(key2);
+    if (it == gmap.end()) {
+      gmap[key2] = groups.size();
+      groups.push_back(BatchGroup{n[k], t, {}});
+      it = gmap.find(key2);
+    }
+    groups[it->second].idx.push_back(k);
+  }
+  // plans, one workspace size for all groups (they run one after another)
+  std::vector<SchurPlan> plans(groups.size());
+  size_t need = 0;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    plan_schur(groups[gi].tier, groups[gi].n, (int)groups[gi].idx.size(), opt ? opt->bottom_modes : 0,
+               &plans[gi]);
+    need = std::max(need, plans[gi].bytes);
+  }
+  TOR_TRY(ensure_cap(w, need));
+  // plan buffer: per group offsets (int64) then output indices (int32); trivial list
+  std::vector<char> meta;
+  std::vector<size_t> meta_off(groups.size());
+  auto align8 = [&]() { while (meta.size() % 8) meta.push_back(0); };
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    align8();
+    meta_off[gi] = meta.size();
+    for (int32_t k : groups[gi].idx) {
+      const int64_t o = offsets[k];
+      meta.insert(meta.end(), (const char*)&o, (const char*)&o + 8);
+    }
+    for (int32_t k : groups[gi].idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
+  }
+  align8();
+  const size_t triv_off = meta.size();
+  for (int32_t k : triv_idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
+  for (int32_t t : triv_tier) meta.insert(meta.end(), (const char*)&t, (const char*)&t + 4);
+  if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size()));
+  if (use_graph) {
+    // capture on a private stream (the caller's may be the null stream, which
+    // cannot be captured), replay on the caller's
+    if (!w->cap_stream) TOR_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = w->cap_stream;
+    hipGraph_t graph = nullptr;
+    TOR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
+                                 opt, out, cs);
+    hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (rc != TOR_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    TOR_HIP(e);
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    TOR_HIP(e);
+    w->graphs[key] = exec;
+    TOR_HIP(hipGraphLaunch(exec, s));
+    return TOR_OK;
+  }
+  return enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed, opt,
+                       out, s);
+}
+
+// ---------------------------------------------------------------------------
+// Precision selector
+// ---------------------------------------------------------------------------
+
+double tier_unit_log10(int t) {
+  return t == TOR_FP64 ? -53.0 * 0.30102999566398120 : (t == TOR_DD ? -104.0 * 0.30102999566398120
+                                                                    : -208.0 * 0.30102999566398120);
+}
+
+// Bound estimate of the significand bits an instance needs (Eq. 7 for
+// floating tiers; see the declaration in tor.h).  feats as tor_features.
+double fallback_bits(const double* f, double tau) {
+  const double n = f[0];
+  const double logdet = -2.0 * f[1];
+  const double a = f[4], k = f[5];
+  const double ln2 = 0.69314718055994531;
+  const double base = 1.0 / ((1.0 - a) - k * n / (1.0 - a)) - 1.0;
+  if (!(base > 0.0)) return 1e300;  // no usable lower bound: take the widest tier
+  const double log2_tor_lower = n * log2(base);
+  const double log2_sabs_upper = n - 0.5 * logdet / ln2;
+  const double b_cancel = std::max(0.0, log2_sabs_upper - log2_tor_lower);
+  const double b_sgn = log2(1.0 / tau);
+  const double b_accum = log2(0.5) + n + 2.0 * log2(n);
+  return b_cancel + b_sgn + b_accum;
+}
+
+// Tiers for the TOR_AUTO instances of a batch; pred/src receive, per
+// instance, the predicted log10 kappa (or the bound's bits in log10 units)
+// and 0 (network) / 1 (bound estimate).
+int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
+                 int batch, double tau, int32_t* tier_of, std::vector<double>* pred,
+                 std::vector<int32_t>* src, hipStream_t s) {
+  pred->assign(batch, 0.0);
+  src->assign(batch, 0);
+  std::vector<int32_t> idx;
+  int nmax = 1;
+  for (int k = 0; k < batch; ++k)
+    if (tier_of[k] == TOR_AUTO && n[k] > 0) {
+      idx.push_back(k);
+      nmax = std::max(nmax, (int)n[k]);
+    }
+  tor_select_stats_t st;
+  memset(&st, 0, sizeof(st));
+  const int m = (int)idx.size();
+  if (m > 0) {
+    tor_selector_t sel;
+    int version;
+    {
+      std::lock_guard<std::mutex> lk(g_sel_mu);
+      sel = g_sel;
+      version = g_sel_version;
+    }
+    // device: offsets, n | feats (m x F) | preds (m) | selector (theta, mean, std)
+    const size_t nsel = TOR_MLP_PARAMS + 2 * TOR_NFEAT;
+    std::vector<char> meta(sizeof(int64_t) * m + sizeof(int32_t) * m);
+    for (int i = 0; i < m; ++i) {
+      memcpy(meta.data() + 8 * i, &offsets[idx[i]], 8);
+      memcpy(meta.data() + 8 * m + 4 * i, &n[idx[i]], 4);
+    }
+    TOR_TRY(upload_meta(w, meta.data(), meta.size()));
+    const size_t o_feat = 0, o_pred = o_feat + sizeof(double) * m * TOR_NFEAT;
+    const size_t o_sel = o_pred + sizeof(double) * m;
+    TOR_TRY(ensure_aux(w, o_sel + sizeof(double) * nsel, s));
+    double* feats = (double*)(w->aux + o_feat);
+    double* preds = (double*)(w->aux + o_pred);
+    double* dsel = (double*)(w->aux + o_sel);
+    TOR_HIP(launch_features((const double2*)O_packed, (const int64_t*)w->meta,
+                            (const int32_t*)(w->meta + 8 * m), m, nmax, feats, s));
+    if (sel.trained) {
+      std::vector<double> hs(nsel);
+      memcpy(hs.data(), sel.theta, sizeof(double) * TOR_MLP_PARAMS);
+      memcpy(hs.data() + TOR_MLP_PARAMS, sel.mean, sizeof(double) * TOR_NFEAT);
+      memcpy(hs.data() + TOR_MLP_PARAMS + TOR_NFEAT, sel.std, sizeof(double) * TOR_NFEAT);
+      TOR_HIP(hipMemcpyAsync(dsel, hs.data(), sizeof(double) * nsel, hipMemcpyHostToDevice, s));
+      TOR_HIP(launch_mlp_forward(dsel, dsel + TOR_MLP_PARAMS, dsel + TOR_MLP_PARAMS + TOR_NFEAT, feats, m,
+                                 preds, s));
+      TOR_HIP(hipStreamSynchronize(s));  // hs must outlive the copy
+    }
+    (void)version;
+    std::vector<double> hf((size_t)m * TOR_NFEAT), hp(m, 0.0);
+    TOR_HIP(hipMemcpyAsync(hf.data(), feats, sizeof(double) * hf.size(), hipMemcpyDeviceToHost, s));
+    if (sel.trained)
+      TOR_HIP(hipMemcpyAsync(hp.data(), preds, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    TOR_HIP(hipStreamSynchronize(s));
+    const double ltau = log10(tau);
+    for (int i = 0; i < m; ++i) {
+      const double* f = &hf[(size_t)i * TOR_NFEAT];
+      const int nk = n[idx[i]];
+      bool ood = !sel.trained || nk < sel.nmin || nk > sel.nmax || !std::isfinite(hp[i]);
+      for (int j = 0; j < TOR_NFEAT && !ood; ++j) {
+        const double span = sel.fmax[j] - sel.fmin[j];
+        const double slack = 0.05 * span + 1e-12;
+        if (!(f[j] >= sel.fmin[j] - slack && f[j] <= sel.fmax[j] + slack)) ood = true;
+      }
+      int t;
+      if (ood) {
+        const double bits = fallback_bits(f, tau);
+        t = bits <= 53.0 ? TOR_FP64 : (bits <= 106.0 ? TOR_DD : TOR_QD);
+        (*pred)[idx[i]] = bits * 0.30102999566398120;
+        (*src)[idx[i]] = 1;
+        st.n_fallback++;
+      } else {
+        t = TOR_QD;
+        for (int c = TOR_FP64; c <= TOR_DD; ++c) {
+          if (sel.log10_c[c] + hp[i] + sel.margin + tier_unit_log10(c) <= ltau) {
+            t = c;
+            break;
+          }
+        }
+        (*pred)[idx[i]] = hp[i];
+        (*src)[idx[i]] = 0;
+      }
+      tier_of[idx[i]] = t;
+      if (t == TOR_FP64) st.n_fp64++;
+      else if (t == TOR_DD) st.n_dd++;
+      else st.n_qd++;
+    }
+  }
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  g_stats = st;
+  return TOR_OK;
+}
+
+// Spot re-evaluation of TOR_AUTO choices one tier up; escalate on a miss.
+int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
+               int batch, const int32_t* tiers_req, double tau, std::vector<int32_t>& tier_of,
+               const std::vector<double>& pred, const std::vector<int32_t>& src, tor_result_t* out,
+               hipStream_t s) {
+  double frac = 1.0 / 32.0;
+  if (const char* e = getenv("TOR_SPOT_FRACTION")) {
+    const double v = atof(e);
+    if (v > 0.0 && v <= 1.0) frac = v;
+  }
+  const int stride = std::max(1, (int)llround(1.0 / frac));
+  int n_spot = 0, n_viol = 0, n_esc = 0;
+  for (int t = TOR_FP64; t <= TOR_DD; ++t) {
+    std::vector<int32_t> cls;
+    for (int k = 0; k < batch; ++k)
+      if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t) cls.push_back(k);
+    if (cls.empty()) continue;
+    std::vector<int32_t> sample;
+    for (size_t i = 0; i < cls.size(); i += stride) sample.push_back(cls[i]);
+    n_spot += (int)sample.size();
+    // re-evaluate the sample one tier up into a scratch result array
+    const size_t rbytes = sizeof(tor_result_t) * batch;
+    TOR_TRY(ensure_aux(w, rbytes, s));
+    tor_result_t* scratch = (tor_result_t*)w->aux;
+    std::vector<int32_t> up(tier_of);
+    for (int32_t k : sample) up[k] = t + 1;
+    TOR_TRY(batch_core(w, O_packed, offsets, n, sample, up, nullptr, scratch, false, s));
+    std::vector<tor_result_t> hi(batch), lo(batch);
+    TOR_HIP(hipMemcpyAsync(hi.data(), scratch, rbytes, hipMemcpyDeviceToHost, s));
+    TOR_HIP(hipMemcpyAsync(lo.data(), out, rbytes, hipMemcpyDeviceToHost, s));
+    TOR_HIP(hipStreamSynchronize(s));
+    double thr = 1e300;
+    bool viol = false;
+    for (int32_t k : sample) {
+      const double th = hi[k].tor[0] + hi[k].tor[1];
+      const double tl = lo[k].tor[0] + lo[k].tor[1];
+      const double err = fabs(tl - th);
+      if (!(err <= tau * fabs(th))) {
+        viol = true;
+        ++n_viol;
+        thr = std::min(thr, pred[k]);
+      }
+    }
+    if (!viol) continue;
+    // move up every instance of this tier predicted at least as hard
+    std::vector<int32_t> esc;
+    for (int32_t k : cls)
+      if (pred[k] >= thr - 1.0 || src[k] == 1) esc.push_back(k);
+    for (int32_t k : esc) tier_of[k] = t + 1;
+    n_esc += (int)esc.size();
+    TOR_TRY(batch_core(w, O_packed, offsets, n, esc, tier_of, nullptr, out, false, s));
+  }
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  g_stats.n_spot = n_spot;
+  g_stats.n_violations = n_viol;
+  g_stats.n_escalated = n_esc;
+  for (int k = 0; k < batch; ++k) (void)k;
   return TOR_OK;
 }
 
@@ -523,6 +829,7 @@ int tor_shutdown(void) {
       for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
       if (w->meta) (void)hipFree(w->meta);
       if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
+      if (w->aux) (void)hipFree(w->aux);
       (void)hipSetDevice(cur);
     }
     delete w;
@@ -572,14 +879,16 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   if (batch == 0) return TOR_OK;
   if (!offsets || !n || !out) return TOR_EINVAL;
   if (opt && opt->algo != TOR_ALGO_AUTO && opt->algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
-  bool any_work = false;
+  bool any_work = false, any_auto = false;
   for (int k = 0; k < batch; ++k) {
     if (n[k] < 0 || n[k] > TOR_NMAX || offsets[k] < 0) return TOR_EINVAL;
     const int t = tiers ? tiers[k] : TOR_AUTO;
     if (t != TOR_FP64 && t != TOR_DD && t != TOR_QD && t != TOR_AUTO) return TOR_EINVAL;
     if (n[k] > 0) any_work = true;
+    if (n[k] > 0 && t == TOR_AUTO) any_auto = true;
   }
   if (any_work && !O_packed) return TOR_EINVAL;
+  if (any_auto && !(tau > 0.0)) return TOR_EINVAL;
   Workspace* w = nullptr;
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
@@ -588,102 +897,182 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
 
   std::vector<int32_t> tier_of(batch);
   for (int k = 0; k < batch; ++k) tier_of[k] = tiers ? tiers[k] : TOR_AUTO;
-  bool any_auto = false;
-  for (int k = 0; k < batch; ++k) any_auto = any_auto || (tier_of[k] == TOR_AUTO && n[k] > 0);
-  if (any_auto) TOR_TRY(select_tiers(w, O_packed, offsets, n, batch, tau, tier_of.data(), s));
+  std::vector<double> pred;
+  std::vector<int32_t> src;
+  if (any_auto) TOR_TRY(select_tiers(w, O_packed, offsets, n, batch, tau, tier_of.data(), &pred, &src, s));
 
   const bool use_graph = opt && (opt->flags & TOR_FLAG_GRAPH);
-  std::string key;
-  if (use_graph) {
-    auto put = [&](const void* p, size_t b) { key.append((const char*)p, b); };
-    put(&O_packed, sizeof(O_packed));
-    put(&out, sizeof(out));
-    put(&s, sizeof(s));
-    put(&batch, sizeof(batch));
-    put(offsets, sizeof(int64_t) * batch);
-    put(n, sizeof(int32_t) * batch);
-    put(tier_of.data(), sizeof(int32_t) * batch);
-    if (opt) put(opt, sizeof(*opt));
-    auto it = w->graphs.find(key);
-    if (it != w->graphs.end()) {
-      TOR_HIP(hipGraphLaunch(it->second, s));
-      return TOR_OK;
-    }
-  }
+  std::vector<int32_t> all(batch);
+  for (int k = 0; k < batch; ++k) all[k] = k;
+  TOR_TRY(batch_core(w, O_packed, offsets, n, all, tier_of, opt, out, use_graph, s));
+  if (any_auto) TOR_TRY(spot_check(w, O_packed, offsets, n, batch, tiers, tau, tier_of, pred, src, out, s));
+  return TOR_OK;
+}
 
-  // group by (n, tier); n = 0 instances are filled directly
-  std::map<std::pair<int, int>, size_t> gmap;
-  std::vector<BatchGroup> groups;
-  std::vector<int32_t> triv_idx, triv_tier;
+int tor_select_tiers(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
+                     double tau, void* stream, int32_t* tiers, double* log10_kappa,
+                     int32_t* source) {
+  if (batch < 0 || !(tau > 0.0)) return TOR_EINVAL;
+  if (batch == 0) return TOR_OK;
+  if (!O_packed || !offsets || !n || !tiers) return TOR_EINVAL;
+  for (int k = 0; k < batch; ++k)
+    if (n[k] < 0 || n[k] > TOR_NMAX || offsets[k] < 0) return TOR_EINVAL;
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  TOR_HIP(hipStreamSynchronize(s));
+  std::vector<int32_t> tier_of(batch, TOR_AUTO);
+  std::vector<double> pred;
+  std::vector<int32_t> src;
+  TOR_TRY(select_tiers(w, O_packed, offsets, n, batch, tau, tier_of.data(), &pred, &src, s));
   for (int k = 0; k < batch; ++k) {
-    const int t = tier_of[k] == TOR_AUTO ? TOR_DD : tier_of[k];
-    if (n[k] == 0) {
-      triv_idx.push_back(k);
-      triv_tier.push_back(t);
-      continue;
-    }
-    auto key2 = std::make_pair(n[k], t);
-    auto it = gmap.find(key2);
-    if (it == gmap.end()) {
-      gmap[key2] = groups.size();
-      groups.push_back(BatchGroup{n[k], t, {}});
-      it = gmap.find(key2);
-    }
-    groups[it->second].idx.push_back(k);
+    tiers[k] = n[k] == 0 ? TOR_FP64 : tier_of[k];
+    if (log10_kappa) log10_kappa[k] = pred[k];
+    if (source) source[k] = src[k];
   }
-  // plans, one workspace size for all groups (they run one after another)
-  std::vector<SchurPlan> plans(groups.size());
-  size_t need = 0;
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    plan_schur(groups[gi].tier, groups[gi].n, (int)groups[gi].idx.size(), opt ? opt->bottom_modes : 0,
-               &plans[gi]);
-    need = std::max(need, plans[gi].bytes);
-  }
-  TOR_TRY(ensure_cap(w, need));
-  // plan buffer: per group offsets (int64) then output indices (int32); trivial list
-  std::vector<char> meta;
-  std::vector<size_t> meta_off(groups.size());
-  auto align8 = [&]() { while (meta.size() % 8) meta.push_back(0); };
-  for (size_t gi = 0; gi < groups.size(); ++gi) {
-    align8();
-    meta_off[gi] = meta.size();
-    for (int32_t k : groups[gi].idx) {
-      const int64_t o = offsets[k];
-      meta.insert(meta.end(), (const char*)&o, (const char*)&o + 8);
+  return TOR_OK;
+}
+
+int tor_last_select_stats(tor_select_stats_t* o) {
+  if (!o) return TOR_EINVAL;
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  *o = g_stats;
+  return TOR_OK;
+}
+
+int tor_selector_set(const tor_selector_t* sel) {
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  if (sel) {
+    if (sel->trained) {
+      for (int i = 0; i < TOR_NFEAT; ++i)
+        if (!(sel->std[i] > 0.0)) return TOR_EINVAL;
+      if (sel->nmin < 1 || sel->nmax < sel->nmin || sel->nmax > TOR_NMAX) return TOR_EINVAL;
     }
-    for (int32_t k : groups[gi].idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
+    g_sel = *sel;
+  } else {
+    memset(&g_sel, 0, sizeof(g_sel));
   }
-  align8();
-  const size_t triv_off = meta.size();
-  for (int32_t k : triv_idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
-  for (int32_t t : triv_tier) meta.insert(meta.end(), (const char*)&t, (const char*)&t + 4);
-  if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size()));
-  // the buffer may have moved: nothing captured before this point survives
-  if (use_graph) {
-    // capture on a private stream (the caller's may be the null stream, which
-    // cannot be captured), replay on the caller's
-    if (!w->cap_stream) TOR_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
-    hipStream_t cs = w->cap_stream;
-    hipGraph_t graph = nullptr;
-    TOR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
-                                 opt, out, cs);
-    hipError_t e = hipStreamEndCapture(cs, &graph);
-    if (rc != TOR_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return rc;
+  ++g_sel_version;
+  return TOR_OK;
+}
+
+int tor_selector_get(tor_selector_t* sel) {
+  if (!sel) return TOR_EINVAL;
+  std::lock_guard<std::mutex> lk(g_sel_mu);
+  *sel = g_sel;
+  return TOR_OK;
+}
+
+int tor_selector_save(const char* path) {
+  if (!path) return TOR_EINVAL;
+  tor_selector_t sel;
+  TOR_TRY(tor_selector_get(&sel));
+  FILE* f = fopen(path, "w");
+  if (!f) return TOR_EINVAL;
+  auto arr = [&](const char* name, const double* v, int cnt) {
+    fprintf(f, "%s %d", name, cnt);
+    for (int i = 0; i < cnt; ++i) fprintf(f, " %.17g", v[i]);
+    fprintf(f, "\n");
+  };
+  fprintf(f, "tor_selector 1\n");
+  arr("theta", sel.theta, TOR_MLP_PARAMS);
+  arr("mean", sel.mean, TOR_NFEAT);
+  arr("std", sel.std, TOR_NFEAT);
+  arr("fmin", sel.fmin, TOR_NFEAT);
+  arr("fmax", sel.fmax, TOR_NFEAT);
+  arr("log10_c", sel.log10_c, 3);
+  arr("margin", &sel.margin, 1);
+  fprintf(f, "nrange %d %d\ntrained %d\n", sel.nmin, sel.nmax, sel.trained);
+  const int ok = fclose(f) == 0;
+  return ok ? TOR_OK : TOR_EINVAL;
+}
+
+int tor_selector_load(const char* path) {
+  if (!path) return TOR_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return TOR_EINVAL;
+  tor_selector_t sel;
+  memset(&sel, 0, sizeof(sel));
+  char name[64];
+  int version = 0, rc = TOR_OK;
+  if (fscanf(f, "%63s %d", name, &version) != 2 || strcmp(name, "tor_selector") != 0 || version != 1)
+    rc = TOR_EINVAL;
+  auto arr = [&](const char* want, double* v, int cnt) {
+    int c = 0;
+    if (rc != TOR_OK) return;
+    if (fscanf(f, "%63s %d", name, &c) != 2 || strcmp(name, want) != 0 || c != cnt) {
+      rc = TOR_EINVAL;
+      return;
     }
-    TOR_HIP(e);
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    TOR_HIP(e);
-    w->graphs[key] = exec;
-    TOR_HIP(hipGraphLaunch(exec, s));
-    return TOR_OK;
+    for (int i = 0; i < cnt; ++i)
+      if (fscanf(f, "%lf", &v[i]) != 1) rc = TOR_EINVAL;
+  };
+  arr("theta", sel.theta, TOR_MLP_PARAMS);
+  arr("mean", sel.mean, TOR_NFEAT);
+  arr("std", sel.std, TOR_NFEAT);
+  arr("fmin", sel.fmin, TOR_NFEAT);
+  arr("fmax", sel.fmax, TOR_NFEAT);
+  arr("log10_c", sel.log10_c, 3);
+  arr("margin", &sel.margin, 1);
+  if (rc == TOR_OK && fscanf(f, "%63s %d %d", name, &sel.nmin, &sel.nmax) != 3) rc = TOR_EINVAL;
+  if (rc == TOR_OK && fscanf(f, "%63s %d", name, &sel.trained) != 2) rc = TOR_EINVAL;
+  fclose(f);
+  if (rc != TOR_OK) return rc;
+  return tor_selector_set(&sel);
+}
+
+double tor_fallback_bits(const double* feats, double tau) { return fallback_bits(feats, tau); }
+
+int tor_features(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
+                 void* stream, double* feats) {
+  if (batch < 0) return TOR_EINVAL;
+  if (batch == 0) return TOR_OK;
+  if (!O_packed || !offsets || !n || !feats) return TOR_EINVAL;
+  int nmax = 1;
+  for (int k = 0; k < batch; ++k) {
+    if (n[k] < 1 || n[k] > TOR_NMAX || offsets[k] < 0) return TOR_EINVAL;
+    nmax = std::max(nmax, (int)n[k]);
   }
-  return enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed, opt,
-                       out, s);
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  TOR_HIP(hipStreamSynchronize(s));
+  std::vector<char> meta(sizeof(int64_t) * batch + sizeof(int32_t) * batch);
+  memcpy(meta.data(), offsets, sizeof(int64_t) * batch);
+  memcpy(meta.data() + sizeof(int64_t) * batch, n, sizeof(int32_t) * batch);
+  TOR_TRY(upload_meta(w, meta.data(), meta.size()));
+  TOR_HIP(launch_features((const double2*)O_packed, (const int64_t*)w->meta,
+                          (const int32_t*)(w->meta + sizeof(int64_t) * batch), batch, nmax, feats, s));
+  return TOR_OK;
+}
+
+int tor_mlp_forward(const double* theta, const double* mean, const double* std, const double* X,
+                    int32_t B, void* stream, double* Y) {
+  if (B < 0 || (B > 0 && (!theta || !mean || !std || !X || !Y))) return TOR_EINVAL;
+  TOR_HIP(launch_mlp_forward(theta, mean, std, X, B, Y, (hipStream_t)stream));
+  return TOR_OK;
+}
+
+int tor_mlp_grad(const double* theta, const double* mean, const double* std, const double* X,
+                 const double* y, int32_t B, double under, double over, void* stream, double* grad,
+                 double* loss) {
+  if (B <= 0 || !theta || !mean || !std || !X || !y || !grad) return TOR_EINVAL;
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = sizeof(double) * ((size_t)B * TOR_MLP_PARAMS + B);
+  TOR_TRY(ensure_aux(w, need, s));
+  double* G = (double*)w->aux;
+  double* lossb = G + (size_t)B * TOR_MLP_PARAMS;
+  TOR_HIP(launch_mlp_grad(theta, mean, std, X, y, B, under, over, G, lossb, grad, loss, s));
+  return TOR_OK;
+}
+
+int tor_mlp_adam(double* theta, const double* grad, double* m, double* v, double lr, double beta1,
+                 double beta2, double eps, int32_t step, void* stream) {
+  if (!theta || !grad || !m || !v || step < 1) return TOR_EINVAL;
+  TOR_HIP(launch_adam(theta, grad, m, v, lr, beta1, beta2, eps, step, (hipStream_t)stream));
+  return TOR_OK;
 }
 
 int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,

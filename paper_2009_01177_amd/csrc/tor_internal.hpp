@@ -86,4 +86,16 @@ hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* 
                        int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st);
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu);
 
+// ---- selector kernels (tor_select.hip) ----
+size_t features_lds_bytes(int nmax);
+hipError_t launch_features(const double2* O, const int64_t* offs, const int32_t* ns, int batch,
+                           int nmax, double* feats, hipStream_t s);
+hipError_t launch_mlp_forward(const double* th, const double* mean, const double* sd,
+                              const double* X, int B, double* Y, hipStream_t s);
+hipError_t launch_mlp_grad(const double* th, const double* mean, const double* sd, const double* X,
+                           const double* y, int B, double under, double over, double* G,
+                           double* lossb, double* grad, double* loss, hipStream_t s);
+hipError_t launch_adam(double* th, const double* grad, double* m, double* v, double lr, double b1,
+                       double b2, double eps, int step, hipStream_t s);
+
 }  // namespace tor

@@ -1,0 +1,158 @@
+"""Precision selector on the GPU: feature kernel and MLP kernels against the
+binary64 reference, training, the TOR_AUTO path's accuracy, the gain of the
+trained network over the bound estimate alone, and spot re-evaluation."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gbs_inputs as g
+from oracle import selector_ref as ref
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tor():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_01177_amd as t
+    t.tor_init()
+    return t
+
+
+def test_features_kernel_matches_reference(tor):
+    Os = [g.random_instance(n, 300 + n) for n in [1, 2, 3, 5, 8, 13, 17, 21]]
+    f = tor.tor_features(tor.Batch(Os)).cpu().numpy()
+    for k, O in enumerate(Os):
+        want = ref.features(O)
+        print(f"[features] n={O.shape[0] // 2}", flush=True)
+        assert np.allclose(f[k], want, rtol=1e-10, atol=1e-10), (k, f[k] - want)
+
+
+def test_mlp_kernels_match_reference(tor):
+    import torch
+    rng = np.random.default_rng(5)
+    P = ref.n_params()
+    theta = rng.normal(0, 0.4, size=P)
+    X = rng.normal(0, 2, size=(300, ref.NFEAT))
+    y = rng.normal(0, 3, size=300)
+    mean = rng.normal(0, 1, size=ref.NFEAT)
+    std = 0.5 + rng.random(ref.NFEAT)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    Y = tor.tor_mlp_forward(d(theta), d(mean), d(std), d(X)).cpu().numpy()
+    assert np.allclose(Y, ref.mlp_forward(theta, X, mean, std), rtol=1e-12, atol=1e-12)
+    grad, loss = tor.tor_mlp_grad(d(theta), d(mean), d(std), d(X), d(y), under=4.0, over=1.0)
+    lw, gw = ref.mlp_loss_and_grad(theta, X, y, mean, std, under=4.0, over=1.0)
+    assert abs(loss.item() - lw) <= 1e-12 * abs(lw)
+    assert np.allclose(grad.cpu().numpy(), gw, rtol=1e-10, atol=1e-13)
+
+
+def test_adam_step_matches_reference(tor):
+    import torch
+    rng = np.random.default_rng(6)
+    P = ref.n_params()
+    th, gr = rng.normal(size=P), rng.normal(size=P)
+    m, v = rng.normal(size=P) * 0.1, rng.random(P) * 0.1
+    lr, b1, b2, eps, step = 1e-2, 0.9, 0.999, 1e-8, 3
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    tt, mm, vv = d(th), d(m), d(v)
+    tor.tor_mlp_adam(tt, d(gr), mm, vv, lr, step, b1, b2, eps)
+    m2 = b1 * m + (1 - b1) * gr
+    v2 = b2 * v + (1 - b2) * gr * gr
+    th2 = th - lr * (m2 / (1 - b1 ** step)) / (np.sqrt(v2 / (1 - b2 ** step)) + eps)
+    assert np.allclose(tt.cpu().numpy(), th2, rtol=1e-14, atol=1e-15)
+    assert np.allclose(mm.cpu().numpy(), m2, rtol=1e-15, atol=0)
+
+
+def _reference_qd(tor, Os):
+    return tor.tor_eval_batched(tor.Batch(Os), tiers="qd")
+
+
+def _meets(res, ref_, tau):
+    bad = []
+    for k, (r, q) in enumerate(zip(res, ref_)):
+        tq = q.exact
+        if tq == 0:
+            continue
+        if float(abs(r.exact - tq) / abs(tq)) > tau:
+            bad.append(k)
+    return bad
+
+
+def test_auto_with_bound_estimate_only_meets_tau(tor):
+    tor.tor_selector_set(None)
+    Os = [O for O in g.batched_workload(batch=200) if O.shape[0] // 2 <= 18][:120]
+    b = tor.Batch(Os)
+    res = tor.tor_eval_batched(b, tau=1e-3)
+    st = tor.tor_last_select_stats()
+    assert st["n_fallback"] == len(Os)
+    assert not _meets(res, _reference_qd(tor, Os), 1e-3)
+
+
+@pytest.fixture(scope="module")
+def trained(tor, tmp_path_factory):
+    from paper_2009_01177_amd import selector
+    path = str(tmp_path_factory.mktemp("sel") / "selector.txt")
+    sel, lab, losses = selector.fit_and_install(count=480, nlo=6, nhi=18, seed=3, epochs=150, path=path)
+    return sel, lab, losses, path
+
+
+def test_training_reduces_the_loss(trained):
+    _, _, losses, _ = trained
+    assert losses[-1] < 0.25 * losses[0]
+
+
+def test_trained_selector_meets_tau_and_gains_over_bounds(tor, trained):
+    """The trained network's tiers meet tau on a held-out batch from the
+    batched workload's state, and route more instances to the FP64 tier
+    than the bound estimate alone would."""
+    sel, _, _, path = trained
+    tor.tor_selector_load(path)
+    Os = [O for O in g.batched_workload(batch=600) if 6 <= O.shape[0] // 2 <= 18][:200]
+    b = tor.Batch(Os)
+    refq = _reference_qd(tor, Os)
+    for tau in (1e-3, 1e-6):
+        res = tor.tor_eval_batched(b, tau=tau)
+        st = tor.tor_last_select_stats()
+        print(f"[selector] tau={tau} {st}", flush=True)
+        assert not _meets(res, refq, tau)
+        t_net, _, src = tor.tor_select_tiers(b, tau)
+        tor.tor_selector_set(None)
+        t_fb, _, _ = tor.tor_select_tiers(b, tau)
+        tor.tor_selector_load(path)
+        cheap_net = int((t_net == 0).sum())
+        cheap_fb = int((t_fb == 0).sum())
+        print(f"[selector] tau={tau} fp64 picks: network {cheap_net}, bounds {cheap_fb}", flush=True)
+        assert cheap_net >= cheap_fb
+    assert cheap_net > cheap_fb or cheap_net == len(Os)
+
+
+def test_spot_check_escalates_a_wrong_choice(tor, trained):
+    """A selector whose FP64 error factor is set far too low picks FP64 where
+    it cannot meet tau; with every such instance spot-checked, the misses are
+    found and moved up a tier."""
+    from paper_2009_01177_amd import _lib
+    _, _, _, path = trained
+    tor.tor_selector_load(path)
+    sel = tor.tor_selector_get()
+    sel.log10_c[0] = -30.0
+    tor.tor_selector_set(sel)
+    Os = [O for O in g.batched_workload(batch=300) if 12 <= O.shape[0] // 2 <= 18][:40]
+    b = tor.Batch(Os)
+    old = os.environ.get("TOR_SPOT_FRACTION")
+    os.environ["TOR_SPOT_FRACTION"] = "1"
+    try:
+        res = tor.tor_eval_batched(b, tau=1e-6)
+        st = tor.tor_last_select_stats()
+    finally:
+        if old is None:
+            del os.environ["TOR_SPOT_FRACTION"]
+        else:
+            os.environ["TOR_SPOT_FRACTION"] = old
+        tor.tor_selector_load(path)
+    print(f"[spot] {st}", flush=True)
+    assert st["n_fp64"] > 0 and st["n_violations"] > 0 and st["n_escalated"] > 0
+    assert not _meets(res, _reference_qd(tor, Os), 1e-6)
