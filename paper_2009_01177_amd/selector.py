@@ -182,3 +182,53 @@ def fit_and_install(count: int = 3000, nlo: int = 6, nhi: int = 24, seed: int = 
         from .api import tor_selector_save
         tor_selector_save(path)
     return sel, lab, losses
+
+
+DEFAULT_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "data",
+                                          "selector_default.txt")
+
+
+def load_default() -> bool:
+    """Install the selector shipped with the library (trained by
+    `python -m paper_2009_01177_amd.selector --train`); False if absent."""
+    import os
+    from .api import tor_selector_load
+    if not os.path.exists(DEFAULT_PATH):
+        return False
+    tor_selector_load(DEFAULT_PATH)
+    return True
+
+
+if __name__ == "__main__":
+    import argparse
+    import sys
+    import time
+    ap = argparse.ArgumentParser(description="train the precision selector on the GPU")
+    ap.add_argument("--train", action="store_true")
+    ap.add_argument("--count", type=int, default=4000)
+    ap.add_argument("--nlo", type=int, default=6)
+    ap.add_argument("--nhi", type=int, default=26)
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--out", default=DEFAULT_PATH)
+    a = ap.parse_args()
+    if not a.train:
+        ap.print_help()
+        sys.exit(0)
+    t0 = time.time()
+    Os = training_instances(a.count, a.nlo, a.nhi, a.seed)
+    print(f"[selector] {len(Os)} instances, n {a.nlo}..{a.nhi}", flush=True)
+    lab = label(Os)
+    print(f"[selector] labelled in {time.time() - t0:.1f} s; log10 kappa "
+          f"{lab.y.min():.2f}..{lab.y.max():.2f}", flush=True)
+    theta, mean, std, losses = train(lab.X, lab.y, epochs=a.epochs, seed=a.seed, log_every=50)
+    log10_c = calibrate(lab)
+    pred = predict(theta, mean, std, lab.X)
+    under = float(np.mean(pred < lab.y))
+    print(f"[selector] loss {losses[0]:.3f} -> {losses[-1]:.4f}; log10 C = {log10_c}; "
+          f"fraction under-predicted {under:.3f}", flush=True)
+    sel = make_selector(theta, mean, std, lab, log10_c)
+    tor_selector_set(sel)
+    from .api import tor_selector_save
+    tor_selector_save(a.out)
+    print(f"[selector] saved {a.out} ({time.time() - t0:.1f} s)", flush=True)
