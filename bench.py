@@ -138,6 +138,62 @@ def cpu_baseline(O, n, seconds: float):
                        f"binary128 per-subset Cholesky, {dt:.1f} s on {threads} threads")
 
 
+def batched_leg(tor, count: int, tau: float, steps: int, check: bool):
+    """Batched workload: `count` click patterns (n ~ U{8..24}) of one 100-mode
+    lossy state; solves/s for fixed DD (graph replay) and for the learned
+    selector (TOR_AUTO: features, network, evaluation, spot re-evaluation)."""
+    import numpy as np
+    import torch
+    import gbs_inputs as g
+    from paper_2009_01177_amd import selector
+    Os = g.batched_workload(batch=count)
+    b = tor.Batch(Os)
+    terms = float(sum(2 ** (O.shape[0] // 2) for O in Os))
+    out = {"workload": f"{count} Torontonians from one 100-mode lossy GBS state (Haar U, "
+                       f"r~U[0.8,1.6], eta=0.3), n~U{{8..24}}", "instances": count, "terms": terms,
+           "tau": tau}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps
+
+    s_dd = timed(lambda: tor.tor_eval_batched(b, tiers="dd", graph=True, sync=False), steps)
+    out["fixed_dd"] = {"s": s_dd, "solves_per_s": count / s_dd, "terms_per_s": terms / s_dd}
+    print(f"[bench] batched fixed DD: {s_dd * 1e3:.1f} ms, {count / s_dd:.0f} solves/s", file=sys.stderr,
+          flush=True)
+    tor.tor_selector_set(None)
+    s_fb = timed(lambda: tor.tor_eval_batched(b, tau=tau, graph=True, sync=False), steps)
+    st_fb = tor.tor_last_select_stats()
+    out["auto_bounds_only"] = {"s": s_fb, "solves_per_s": count / s_fb, "stats": st_fb}
+    have = selector.load_default()
+    s_ml = timed(lambda: tor.tor_eval_batched(b, tau=tau, graph=True, sync=False), steps)
+    st_ml = tor.tor_last_select_stats()
+    out["auto_learned"] = {"s": s_ml, "solves_per_s": count / s_ml, "stats": st_ml,
+                           "selector": "paper_2009_01177_amd/data/selector_default.txt" if have else None}
+    out["gain_learned_vs_fixed_dd"] = s_dd / s_ml
+    out["gain_learned_vs_bounds_only"] = s_fb / s_ml
+    print(f"[bench] batched auto: bounds-only {s_fb * 1e3:.1f} ms, learned {s_ml * 1e3:.1f} ms "
+          f"({st_ml})", file=sys.stderr, flush=True)
+    if check:
+        res = tor.tor_eval_batched(b, tau=tau)
+        ref = tor.tor_eval_batched(b, tiers="qd")
+        dd = tor.tor_eval_batched(b, tiers="dd")
+        worst = 0.0
+        worst_dd = 0.0
+        for r, q, d in zip(res, ref, dd):
+            tq = q.exact
+            if tq != 0:
+                worst = max(worst, float(abs(r.exact - tq) / abs(tq)))
+                worst_dd = max(worst_dd, float(abs(d.exact - tq) / abs(tq)))
+        out["max_rel_err_vs_qd"] = {"auto_learned": worst, "fixed_dd": worst_dd}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -152,6 +208,10 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=4096, help="batched leg instances (0: skip)")
+    ap.add_argument("--tau", type=float, default=1e-3)
+    ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--batch-check", action="store_true", help="check the batched leg against QD")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -225,6 +285,8 @@ def main():
         "algorithmic_flops_all_kernels": (schur_flops(n, args.tier) + (1 << n) * acc_flops(args.tier))
         if algo == "schur" else flops,
     }
+    if args.batch > 0:
+        line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(O, n, args.cpu_seconds)

@@ -12,6 +12,7 @@ tor_mlp_adam); this module only drives them.
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass
 
 import numpy as np
@@ -184,14 +185,12 @@ def fit_and_install(count: int = 3000, nlo: int = 6, nhi: int = 24, seed: int = 
     return sel, lab, losses
 
 
-DEFAULT_PATH = __import__("os").path.join(__import__("os").path.dirname(__file__), "data",
-                                          "selector_default.txt")
+DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector_default.txt")
 
 
 def load_default() -> bool:
     """Install the selector shipped with the library (trained by
     `python -m paper_2009_01177_amd.selector --train`); False if absent."""
-    import os
     from .api import tor_selector_load
     if not os.path.exists(DEFAULT_PATH):
         return False
