@@ -40,7 +40,13 @@ struct Workspace {
   std::map<std::pair<int, int>, ItemTable> tables;  // (n, d) -> prefix items
   char* meta = nullptr;         // device copy of the batch plan (offsets, indices, tiers)
   size_t meta_cap = 0;
-  std::map<std::string, hipGraphExec_t> graphs;  // captured batches (TOR_FLAG_GRAPH)
+  // captured batches (TOR_FLAG_GRAPH); each owns a private device copy of its
+  // plan, since the shared plan buffer is rewritten by every later call
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    char* plan = nullptr;
+  };
+  std::map<std::string, GraphEntry> graphs;
   hipStream_t cap_stream = nullptr;              // private stream graphs are captured on
   char* aux = nullptr;                           // selector scratch
   size_t aux_cap = 0;
@@ -76,6 +82,16 @@ int record_ev(Workspace* w, int k, hipStream_t s) {
   }
   TOR_HIP(hipEventRecord(w->evs[k], s));
   return TOR_OK;
+}
+
+// Release every captured graph and its plan copy (after the device has
+// finished with them).
+void drop_graphs(Workspace* w) {
+  for (auto& kv : w->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    if (kv.second.plan) (void)hipFree(kv.second.plan);
+  }
+  w->graphs.clear();
 }
 
 // Sum the recorded launch durations (after the stream has synchronised).
@@ -137,8 +153,7 @@ int ensure_cap(Workspace* w, size_t bytes) {
     w->cap = 0;
   }
   // captured graphs point into the old buffer
-  for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
-  w->graphs.clear();
+  drop_graphs(w);
   TOR_HIP(hipMalloc((void**)&w->buf, ncap));
   w->cap = ncap;
   return TOR_OK;
@@ -436,7 +451,10 @@ struct BatchGroup {
   std::vector<int32_t> idx;  // instance indices
 };
 
-int upload_meta(Workspace* w, const void* src, size_t bytes) {
+// Copy a plan into the shared plan buffer.  Earlier work on stream s may still
+// read the buffer, so wait for it first.
+int upload_meta(Workspace* w, const void* src, size_t bytes, hipStream_t s) {
+  TOR_HIP(hipStreamSynchronize(s));
   if (bytes > w->meta_cap) {
     if (w->meta) TOR_HIP(hipFree(w->meta));
     w->meta = nullptr;
@@ -445,24 +463,22 @@ int upload_meta(Workspace* w, const void* src, size_t bytes) {
     while (cap < bytes) cap *= 2;
     TOR_HIP(hipMalloc((void**)&w->meta, cap));
     w->meta_cap = cap;
-    for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
-    w->graphs.clear();
   }
   TOR_HIP(hipMemcpy(w->meta, src, bytes, hipMemcpyHostToDevice));
   return TOR_OK;
 }
 
-// Enqueue every group of a batch (plan already uploaded to w->meta).
-int enqueue_batch(Workspace* w, const std::vector<BatchGroup>& groups,
+// Enqueue every group of a batch whose plan is at `plan` (device).
+int enqueue_batch(Workspace* w, const char* plan, const std::vector<BatchGroup>& groups,
                   const std::vector<SchurPlan>& plans, const std::vector<size_t>& meta_off,
                   size_t triv_off, int ntriv, const void* O_packed, const tor_options_t* opt,
                   tor_result_t* out, hipStream_t s) {
   if (ntriv > 0)
-    TOR_HIP(launch_fill_trivial(out, (const int32_t*)(w->meta + triv_off),
-                                (const int32_t*)(w->meta + triv_off) + ntriv, ntriv, s));
+    TOR_HIP(launch_fill_trivial(out, (const int32_t*)(plan + triv_off),
+                                (const int32_t*)(plan + triv_off) + ntriv, ntriv, s));
   for (size_t gi = 0; gi < groups.size(); ++gi) {
     const BatchGroup& g = groups[gi];
-    const int64_t* offs = (const int64_t*)(w->meta + meta_off[gi]);
+    const int64_t* offs = (const int64_t*)(plan + meta_off[gi]);
     const int32_t* oidx = (const int32_t*)(offs + g.idx.size());
     TOR_TRY(enqueue_schur_group(w, plans[gi], O_packed, offs, 2 * (int64_t)g.n, opt, oidx, out, false, s));
   }
@@ -509,7 +525,7 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
     if (opt) put(opt, sizeof(*opt));
     auto it = w->graphs.find(key);
     if (it != w->graphs.end()) {
-      TOR_HIP(hipGraphLaunch(it->second, s));
+      TOR_HIP(hipGraphLaunch(it->second.exec, s));
       return TOR_OK;
     }
   }
@@ -560,32 +576,50 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
   const size_t triv_off = meta.size();
   for (int32_t k : triv_idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
   for (int32_t t : triv_tier) meta.insert(meta.end(), (const char*)&t, (const char*)&t + 4);
-  if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size()));
   if (use_graph) {
+    if (w->graphs.size() >= 64) {  // bound the cache
+      TOR_HIP(hipDeviceSynchronize());
+      drop_graphs(w);
+    }
+    // the graph keeps its own copy of the plan
+    Workspace::GraphEntry ge;
+    if (!meta.empty()) {
+      TOR_HIP(hipMalloc((void**)&ge.plan, meta.size()));
+      hipError_t e0 = hipMemcpy(ge.plan, meta.data(), meta.size(), hipMemcpyHostToDevice);
+      if (e0 != hipSuccess) {
+        (void)hipFree(ge.plan);
+        return hip_err(e0);
+      }
+    }
     // capture on a private stream (the caller's may be the null stream, which
     // cannot be captured), replay on the caller's
     if (!w->cap_stream) TOR_HIP(hipStreamCreateWithFlags(&w->cap_stream, hipStreamNonBlocking));
     hipStream_t cs = w->cap_stream;
     hipGraph_t graph = nullptr;
-    TOR_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    const int rc = enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
-                                 opt, out, cs);
-    hipError_t e = hipStreamEndCapture(cs, &graph);
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = hip_err(e);
+    if (rc == TOR_OK) {
+      rc = enqueue_batch(w, ge.plan, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
+                         opt, out, cs);
+      e = hipStreamEndCapture(cs, &graph);
+      if (rc == TOR_OK) rc = hip_err(e);
+    }
+    if (rc == TOR_OK) {
+      e = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+      rc = hip_err(e);
+    }
+    if (graph) (void)hipGraphDestroy(graph);
     if (rc != TOR_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
+      if (ge.plan) (void)hipFree(ge.plan);
       return rc;
     }
-    TOR_HIP(e);
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    TOR_HIP(e);
-    w->graphs[key] = exec;
-    TOR_HIP(hipGraphLaunch(exec, s));
+    w->graphs[key] = ge;
+    TOR_HIP(hipGraphLaunch(ge.exec, s));
     return TOR_OK;
   }
-  return enqueue_batch(w, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed, opt,
-                       out, s);
+  if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size(), s));
+  return enqueue_batch(w, w->meta, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
+                       opt, out, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -647,7 +681,7 @@ int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, con
       memcpy(meta.data() + 8 * i, &offsets[idx[i]], 8);
       memcpy(meta.data() + 8 * m + 4 * i, &n[idx[i]], 4);
     }
-    TOR_TRY(upload_meta(w, meta.data(), meta.size()));
+    TOR_TRY(upload_meta(w, meta.data(), meta.size(), s));
     const size_t o_feat = 0, o_pred = o_feat + sizeof(double) * m * TOR_NFEAT;
     const size_t o_sel = o_pred + sizeof(double) * m;
     TOR_TRY(ensure_aux(w, o_sel + sizeof(double) * nsel, s));
@@ -826,7 +860,7 @@ int tor_shutdown(void) {
       if (w->host_res) (void)hipHostFree(w->host_res);
       if (w->host_lev) (void)hipHostFree(w->host_lev);
       for (hipEvent_t e : w->evs) (void)hipEventDestroy(e);
-      for (auto& kv : w->graphs) (void)hipGraphExecDestroy(kv.second);
+      drop_graphs(w);
       if (w->meta) (void)hipFree(w->meta);
       if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
       if (w->aux) (void)hipFree(w->aux);
@@ -1040,7 +1074,7 @@ int tor_features(const void* O_packed, const int64_t* offsets, const int32_t* n,
   std::vector<char> meta(sizeof(int64_t) * batch + sizeof(int32_t) * batch);
   memcpy(meta.data(), offsets, sizeof(int64_t) * batch);
   memcpy(meta.data() + sizeof(int64_t) * batch, n, sizeof(int32_t) * batch);
-  TOR_TRY(upload_meta(w, meta.data(), meta.size()));
+  TOR_TRY(upload_meta(w, meta.data(), meta.size(), s));
   TOR_HIP(launch_features((const double2*)O_packed, (const int64_t*)w->meta,
                           (const int32_t*)(w->meta + sizeof(int64_t) * batch), batch, nmax, feats, s));
   return TOR_OK;

@@ -156,3 +156,23 @@ def test_spot_check_escalates_a_wrong_choice(tor, trained):
     print(f"[spot] {st}", flush=True)
     assert st["n_fp64"] > 0 and st["n_violations"] > 0 and st["n_escalated"] > 0
     assert not _meets(res, _reference_qd(tor, Os), 1e-6)
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_auto_graph_replays_survive_spot_checks(tor, trained, learned):
+    """Regression: TOR_AUTO with graph capture, called repeatedly.  Each call
+    runs spot re-evaluations, which evaluate other plans between replays of
+    the captured graph; every replay must equal the uncaptured result."""
+    _, _, _, path = trained
+    if learned:
+        tor.tor_selector_load(path)
+    else:
+        tor.tor_selector_set(None)
+    Os = [O for O in g.batched_workload(batch=400) if 8 <= O.shape[0] // 2 <= 20][:150]
+    b = tor.Batch(Os)
+    base = tor.tor_eval_batched(b, tau=1e-3)
+    for rep in range(3):
+        b.out.zero_()
+        got = tor.tor_eval_batched(b, tau=1e-3, graph=True)
+        assert [r.expansion for r in got] == [r.expansion for r in base], rep
+    tor.tor_selector_load(path)
