@@ -151,10 +151,12 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
  * The call waits for `stream` to drain, uploads the batch plan, then
  * enqueues the evaluation and returns without waiting for it.  With
  * TOR_AUTO instances it is synchronous: the tiers are chosen first, and a
- * sample of the instances given FP64 or DD (1/32 of each, at least one;
- * TOR_SPOT_FRACTION overrides) is re-evaluated one tier up; when a sample
- * misses tau, every instance of that tier predicted at least as hard is
- * re-evaluated one tier up (tor_last_select_stats reports the counts). */
+ * sample of the network's FP64 and DD choices whose predicted error lies
+ * within 4 decades of tau (1/32 of them, at least one per tier;
+ * TOR_SPOT_FRACTION and TOR_SPOT_WINDOW override) is re-evaluated one tier
+ * up; when a sample misses tau, every instance of that tier predicted at
+ * least as hard is re-evaluated one tier up (tor_last_select_stats reports
+ * the counts). */
 int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
                      const int32_t* tiers, double tau, const tor_options_t* opt, void* stream,
                      tor_result_t* out);

@@ -746,6 +746,10 @@ int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, con
 }
 
 // Spot re-evaluation of TOR_AUTO choices one tier up; escalate on a miss.
+// Only network choices whose predicted error lies within `window` decades
+// of tau are informative (a choice predicted far below tau cannot be
+// checked against tau by a re-evaluation that is itself only as good as the
+// next tier); a fraction of those is re-evaluated, at least one per tier.
 int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
                int batch, const int32_t* tiers_req, double tau, std::vector<int32_t>& tier_of,
                const std::vector<double>& pred, const std::vector<int32_t>& src, tor_result_t* out,
@@ -755,15 +759,31 @@ int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const
     const double v = atof(e);
     if (v > 0.0 && v <= 1.0) frac = v;
   }
+  double window = 4.0;
+  if (const char* e = getenv("TOR_SPOT_WINDOW")) {
+    const double v = atof(e);
+    if (v > 0.0) window = v;
+  }
+  tor_selector_t sel;
+  {
+    std::lock_guard<std::mutex> lk(g_sel_mu);
+    sel = g_sel;
+  }
+  const double ltau = log10(tau);
   const int stride = std::max(1, (int)llround(1.0 / frac));
   int n_spot = 0, n_viol = 0, n_esc = 0;
   for (int t = TOR_FP64; t <= TOR_DD; ++t) {
-    std::vector<int32_t> cls;
-    for (int k = 0; k < batch; ++k)
-      if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t) cls.push_back(k);
-    if (cls.empty()) continue;
+    std::vector<int32_t> cls, near;
+    for (int k = 0; k < batch; ++k) {
+      if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t) {
+        cls.push_back(k);
+        const double lerr = sel.log10_c[t] + pred[k] + sel.margin + tier_unit_log10(t);
+        if (src[k] == 0 && lerr >= ltau - window) near.push_back(k);
+      }
+    }
+    if (near.empty()) continue;
     std::vector<int32_t> sample;
-    for (size_t i = 0; i < cls.size(); i += stride) sample.push_back(cls[i]);
+    for (size_t i = 0; i < near.size(); i += stride) sample.push_back(near[i]);
     n_spot += (int)sample.size();
     // re-evaluate the sample one tier up into a scratch result array
     const size_t rbytes = sizeof(tor_result_t) * batch;

@@ -142,16 +142,18 @@ def test_spot_check_escalates_a_wrong_choice(tor, trained):
     tor.tor_selector_set(sel)
     Os = [O for O in g.batched_workload(batch=300) if 12 <= O.shape[0] // 2 <= 18][:40]
     b = tor.Batch(Os)
-    old = os.environ.get("TOR_SPOT_FRACTION")
+    old = {k: os.environ.get(k) for k in ("TOR_SPOT_FRACTION", "TOR_SPOT_WINDOW")}
     os.environ["TOR_SPOT_FRACTION"] = "1"
+    os.environ["TOR_SPOT_WINDOW"] = "100"  # the doctored factor puts every prediction far below tau
     try:
         res = tor.tor_eval_batched(b, tau=1e-6)
         st = tor.tor_last_select_stats()
     finally:
-        if old is None:
-            del os.environ["TOR_SPOT_FRACTION"]
-        else:
-            os.environ["TOR_SPOT_FRACTION"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
         tor.tor_selector_load(path)
     print(f"[spot] {st}", flush=True)
     assert st["n_fp64"] > 0 and st["n_violations"] > 0 and st["n_escalated"] > 0
