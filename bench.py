@@ -212,6 +212,9 @@ def main():
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-check", action="store_true", help="check the batched leg against QD")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="first copy this many bytes device-to-device (a known-size kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -224,6 +227,13 @@ def main():
     import torch
     import gbs_inputs as g
     import paper_2009_01177_amd as tor
+
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     n = args.n
     O, modes = g.workload("n30_lossy", n=n)
