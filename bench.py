@@ -92,6 +92,26 @@ def paper_eq9_flops(n: int) -> float:
     return sum(math.comb(n, i) * (32.0 / 3 * i ** 3 + 4 * i * i - 8.0 / 3 * i) for i in range(1, n + 1))
 
 
+def measured_traffic(tier: str, n: int, algo: str):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "leaf_kernel_n30_traffic.txt")
+    src = os.path.join(ROOT, "paper_2009_01177_amd", "csrc", "tor_schur.hip")
+    if algo != "schur" or n != 30 or not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.strip().split("=", 1)
+            kv[k] = v
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_sha256_prefix") != sha:
+        return None
+    v = kv.get(f"{tier}_traffic_bytes")
+    return int(v) if v else None
+
+
 def time_tier(tor, Od, tier, steps, warmup, algo="auto", split=-1, sb=0):
     import torch
     for _ in range(warmup):
@@ -277,7 +297,8 @@ def main():
                    "n": n, "terms": int(terms), "tier": args.tier, "algo": algo,
                    "split_depth": d_used, "grid": grid_used},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                     "traffic": measured_traffic(args.tier, n, algo),
                      "kernel": "leaf_kernel" if algo == "schur" else "border_kernel",
                      "launches_per_step": launches,
                      "kernel_ms_per_launch": kernel_ms / max(launches, 1),
