@@ -186,6 +186,20 @@ int tor_debug_sampled_terms(const void* O, int32_t n, int64_t ld, int32_t tier,
  * *grid the workgroups per launch.  Any pointer may be NULL.  -1 if none. */
 double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches);
 
+/* ---- Autotuner -------------------------------------------------------------
+ * The Schur path's only shape choice with a real trade-off is s_b, the modes
+ * each lane finishes in registers (more registers per lane vs. fewer middle
+ * levels in LDS).  The tuner times every compiled s_b for (n, tier) on a
+ * synthetic instance (the work does not depend on the values) and makes the
+ * fastest the default for that (n, tier) in this process. */
+
+/* best_bottom: host, the chosen s_b; ms: host, 5 doubles (s_b = 1..5, -1
+ * where not compiled for the tier), may be NULL.  Synchronous; 1 <= n <= TOR_NMAX. */
+int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, double* ms);
+/* Save / load the tuned table as text lines "n tier s_b". */
+int tor_autotune_save(const char* path);
+int tor_autotune_load(const char* path);
+
 /* ---- Precision selector (TOR_AUTO) --------------------------------------
  * The paper picks its precision once per run from bounds on the largest and
  * smallest intermediate values (Sec. 5.4, Eq. 5-7).  Here a small network

@@ -27,6 +27,7 @@ EXPORTS = (
     "tor_features", "tor_mlp_forward", "tor_mlp_grad", "tor_mlp_adam",
     "tor_selector_set", "tor_selector_get", "tor_selector_save", "tor_selector_load",
     "tor_fallback_bits", "tor_select_tiers", "tor_last_select_stats",
+    "tor_autotune", "tor_autotune_save", "tor_autotune_load",
 )
 
 TOR_NFEAT = 12
@@ -148,6 +149,12 @@ def lib():
                                    ctypes.POINTER(i32), pd, ctypes.POINTER(i32)]
     L.tor_last_select_stats.restype = ctypes.c_int
     L.tor_last_select_stats.argtypes = [ctypes.POINTER(TorSelectStatsC)]
+    L.tor_autotune.restype = ctypes.c_int
+    L.tor_autotune.argtypes = [i32, i32, vp, ctypes.POINTER(i32), pd]
+    L.tor_autotune_save.restype = ctypes.c_int
+    L.tor_autotune_save.argtypes = [ctypes.c_char_p]
+    L.tor_autotune_load.restype = ctypes.c_int
+    L.tor_autotune_load.argtypes = [ctypes.c_char_p]
     L.tor_next_mask.restype = u64
     L.tor_next_mask.argtypes = [u64]
     L.tor_kth_mask.restype = u64

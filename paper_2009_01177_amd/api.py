@@ -174,6 +174,23 @@ def tor_eval_batched(batch: "Batch", tiers=None, tau: float = 1e-3, graph: bool 
     return _results_from(batch.out[:B].cpu().numpy())
 
 
+def tor_autotune(n: int, tier="dd", stream=None):
+    """(best s_b, times in ms for s_b = 1..5, -1 where not run)."""
+    best = ctypes.c_int32(0)
+    ms = np.zeros(5, dtype=np.float64)
+    check(lib().tor_autotune(int(n), tier_id(tier), _stream_ptr(stream), ctypes.byref(best),
+                             ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tor_autotune")
+    return int(best.value), ms
+
+
+def tor_autotune_save(path: str):
+    check(lib().tor_autotune_save(str(path).encode()), "tor_autotune_save")
+
+
+def tor_autotune_load(path: str):
+    check(lib().tor_autotune_load(str(path).encode()), "tor_autotune_load")
+
+
 # ---- precision selector ----------------------------------------------------
 
 def _dptr_t(t):

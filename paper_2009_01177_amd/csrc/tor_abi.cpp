@@ -59,6 +59,15 @@ struct Workspace {
 std::mutex g_mu;
 std::map<int, Workspace*> g_ws;
 
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, int> g_tuned;  // (n, tier) -> s_b
+
+int tuned_bottom(int n, int tier) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tuned.find(std::make_pair(n, tier));
+  return it == g_tuned.end() ? 0 : it->second;
+}
+
 std::mutex g_sel_mu;
 tor_selector_t g_sel;  // zero-initialised: no network
 int g_sel_version = 0;
@@ -323,6 +332,7 @@ void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
   p->tier = tier;
   p->n = n;
   p->R = R;
+  if (sb_req <= 0) sb_req = tuned_bottom(n, tier);
   schur_levels(tier, n, sb_req, &p->s_m, &p->s_b);
   p->D_m = n - p->s_m;
   p->rb = schur_value_bytes(tier);
@@ -984,6 +994,90 @@ int tor_select_tiers(const void* O_packed, const int64_t* offsets, const int32_t
     if (log10_kappa) log10_kappa[k] = pred[k];
     if (source) source[k] = src[k];
   }
+  return TOR_OK;
+}
+
+int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, double* ms) {
+  if (n < 1 || n > TOR_NMAX || (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD)) return TOR_EINVAL;
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  // synthetic instance: O = 0.25 I (a thermal product), positive definite
+  std::vector<double> h((size_t)8 * n * n, 0.0);
+  for (int i = 0; i < 2 * n; ++i) h[2 * ((size_t)i * 2 * n + i)] = 0.25;
+  double* dO = nullptr;
+  TOR_HIP(hipMalloc((void**)&dO, sizeof(double) * h.size()));
+  int rc = hip_err(hipMemcpy(dO, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+  const int cand_max = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
+  int best = 0;
+  double best_ms = 1e300;
+  for (int sb = 1; sb <= 5; ++sb) {
+    if (ms) ms[sb - 1] = -1.0;
+    if (rc != TOR_OK || sb > cand_max || sb > n) continue;
+    tor_options_t o;
+    memset(&o, 0, sizeof(o));
+    o.algo = TOR_ALGO_SCHUR;
+    o.split_depth = -1;
+    o.bottom_modes = sb;
+    o.flags = TOR_FLAG_TIME_KERNEL;
+    tor_result_t r;
+    double tot = 0.0;
+    for (int rep = 0; rep < 3 && rc == TOR_OK; ++rep) {
+      hipEvent_t a, b;
+      rc = hip_err(hipEventCreate(&a));
+      if (rc != TOR_OK) break;
+      rc = hip_err(hipEventCreate(&b));
+      if (rc == TOR_OK) rc = hip_err(hipEventRecord(a, s));
+      if (rc == TOR_OK) rc = tor_eval(dO, n, 2 * n, tier, &o, stream, &r);
+      if (rc == TOR_OK) rc = hip_err(hipEventRecord(b, s));
+      if (rc == TOR_OK) rc = hip_err(hipEventSynchronize(b));
+      float t = 0.0f;
+      if (rc == TOR_OK) rc = hip_err(hipEventElapsedTime(&t, a, b));
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      if (rep > 0) tot += t;  // the first run warms up
+    }
+    if (rc != TOR_OK) break;
+    const double t = tot / 2.0;
+    if (ms) ms[sb - 1] = t;
+    if (t < best_ms) {
+      best_ms = t;
+      best = sb;
+    }
+  }
+  (void)hipFree(dO);
+  if (rc != TOR_OK) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_pair((int)n, (int)tier)] = best;
+  }
+  if (best_bottom) *best_bottom = best;
+  return TOR_OK;
+}
+
+int tor_autotune_save(const char* path) {
+  if (!path) return TOR_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return TOR_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : g_tuned) fprintf(f, "%d %d %d\n", kv.first.first, kv.first.second, kv.second);
+  return fclose(f) == 0 ? TOR_OK : TOR_EINVAL;
+}
+
+int tor_autotune_load(const char* path) {
+  if (!path) return TOR_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return TOR_EINVAL;
+  std::map<std::pair<int, int>, int> t;
+  int a, b, c, rc = TOR_OK;
+  while (fscanf(f, "%d %d %d", &a, &b, &c) == 3) {
+    if (a < 1 || a > TOR_NMAX || b < TOR_FP64 || b > TOR_QD || c < 1 || c > 5) rc = TOR_EINVAL;
+    t[std::make_pair(a, b)] = c;
+  }
+  fclose(f);
+  if (rc != TOR_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (auto& kv : t) g_tuned[kv.first] = kv.second;
   return TOR_OK;
 }
 

@@ -83,3 +83,18 @@ def test_argument_checks_need_no_gpu(L):
     assert L.tor_eval(None, 0, 0, 1, None, None, ctypes.byref(out)) == 0
     assert out.tor[0] == 1.0 and out.abs_sum[0] == 1.0
     assert L.tor_strerror(_lib.TOR_ENOTPD).decode().startswith("I - O")
+
+
+def test_autotune_table_round_trip_needs_no_gpu(tmp_path):
+    import paper_2009_01177_amd as tor
+    p = tmp_path / "t.txt"
+    p.write_text("30 1 3\n24 0 5\n")
+    tor.tor_autotune_load(str(p))
+    q = tmp_path / "u.txt"
+    tor.tor_autotune_save(str(q))
+    lines = set(q.read_text().split("\n"))
+    assert {"30 1 3", "24 0 5"} <= lines
+    bad = tmp_path / "bad.txt"
+    bad.write_text("30 7 3\n")
+    with pytest.raises(tor.TorError):
+        tor.tor_autotune_load(str(bad))

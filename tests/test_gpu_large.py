@@ -1,0 +1,101 @@
+"""Full-size checks of the benchmark workloads (n = 30, 36, 40) and the
+largest n the library accepts: sampled terms against the binary128 oracle,
+closed forms of product states at the full size, agreement between tiers,
+and the autotuner."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import gbs_inputs as g
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tor():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_01177_amd as t
+    t.tor_init()
+    return t
+
+
+def _sampled(tor, O, n, tier, k, seed, tol):
+    rng = np.random.default_rng(seed)
+    masks = rng.integers(0, 1 << n, size=k, dtype=np.uint64)
+    masks[:3] = [0, (1 << n) - 1, 1 << (n - 1)]
+    print(f"[large] sampled terms n={n} tier={tier} k={k}", flush=True)
+    got = tor.tor_debug_sampled_terms(O, masks, tier=tier)
+    _, want, st = oracle.terms_exact(O, masks)
+    assert (st == 0).all()
+    for i in range(k):
+        gv = sum((Fraction(x) for x in got[i]), Fraction(0))
+        assert float(abs(gv - want[i]) / abs(want[i])) < tol, (i, int(masks[i]))
+
+
+@pytest.mark.parametrize("name,n", [("n36_stress", 36), ("n40_lossy", 40)])
+@pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("dd", 1e-27), ("qd", 1e-31)])
+def test_sampled_terms_full_size(tor, name, n, tier, tol):
+    O, _ = g.workload(name)
+    _sampled(tor, O, n, tier, 120, n, tol)
+
+
+@pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("dd", 1e-27)])
+def test_sampled_terms_at_the_largest_n(tor, tier, tol):
+    O = g.random_instance(48, 4848, M=60)
+    _sampled(tor, O, 48, tier, 40, 48, tol)
+
+
+def _block_state(n, seed):
+    from test_gpu_parity import _block_state as bs
+    return bs(n, seed)
+
+
+@pytest.mark.parametrize("n", [36, 40])
+def test_block_diagonal_closed_form_full_size(tor, n):
+    """Product states at the full sizes through the Schur path (DD), against
+    the exact product of 60-digit block values."""
+    O, prod, sabs = _block_state(n, 1000 + n)
+    print(f"[large] block-diagonal n={n} dd", flush=True)
+    res = tor.tor_eval(O, tier="dd")
+    assert float(abs(res.exact - prod) / sabs) <= 1e-25
+
+
+def test_tiers_agree_on_the_n30_workload(tor):
+    """FP64 and DD against QD on the benchmark's own instance (kappa 2.6e21)."""
+    O, _ = g.workload("n30_lossy")
+    q = tor.tor_eval(O, tier="qd")
+    d = tor.tor_eval(O, tier="dd")
+    f = tor.tor_eval(O, tier="fp64")
+    sabs = q.abs_exact
+    print(f"[large] n30 kappa={q.kappa:.3e}", flush=True)
+    assert float(abs(d.exact - q.exact) / sabs) <= 1e-25
+    assert float(abs(f.exact - q.exact) / sabs) <= 1e-12
+    # DD keeps about kappa * n * 2^-104 of relative accuracy: 8 digits here
+    assert float(abs(d.exact - q.exact) / abs(q.exact)) < 1e-6
+
+
+def test_tiers_agree_on_the_n36_stress_workload(tor):
+    O, _ = g.workload("n36_stress")
+    d = tor.tor_eval(O, tier="dd")
+    f = tor.tor_eval(O, tier="fp64")
+    assert float(abs(f.exact - d.exact) / d.abs_exact) <= 1e-12
+
+
+def test_autotuner(tor, tmp_path):
+    best, ms = tor.tor_autotune(20, "dd")
+    print(f"[large] autotune n=20 dd best={best} ms={ms}", flush=True)
+    assert 1 <= best <= 4 and ms[best - 1] > 0
+    assert ms[best - 1] == min(x for x in ms if x > 0)
+    p = str(tmp_path / "tune.txt")
+    tor.tor_autotune_save(p)
+    tor.tor_autotune_load(p)
+    assert f"20 1 {best}" in open(p).read()
+    # the tuned default still matches the oracle
+    from test_gpu_parity import ladder
+    O, ref = ladder(20)
+    res = tor.tor_eval(O, tier="dd")
+    assert float(abs(res.exact - ref["tor"]) / ref["abs_sum"]) <= 1e-25
