@@ -37,10 +37,21 @@ def _sampled(tor, O, n, tier, k, seed, tol):
 
 
 @pytest.mark.parametrize("name,n", [("n36_stress", 36), ("n40_lossy", 40)])
-@pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("dd", 1e-27), ("qd", 1e-31)])
+@pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("dd", 1e-27)])
 def test_sampled_terms_full_size(tor, name, n, tier, tol):
     O, _ = g.workload(name)
     _sampled(tor, O, n, tier, 120, n, tol)
+
+
+def test_sampled_terms_qd_largest_factor_in_lds(tor):
+    """QD single-subset terms use the bordered kernel, whose quad-double factor
+    fits LDS up to n = 34; larger n is refused with TOR_EUNSUPPORTED."""
+    O, _ = g.workload("n40_lossy", n=34)
+    _sampled(tor, O, 34, "qd", 60, 34, 1e-31)
+    O36, _ = g.workload("n36_stress")
+    with pytest.raises(tor.TorError) as e:
+        tor.tor_debug_sampled_terms(O36, np.array([1], dtype=np.uint64), tier="qd")
+    assert e.value.code == -5
 
 
 @pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("dd", 1e-27)])
