@@ -42,9 +42,9 @@ if ROOT not in sys.path:
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
 # FP64 operations per complex multiply-add in each tier's arithmetic:
 #   FP64: 4 fused multiply-adds = 8 flops;
-#   DD  : 4 double-double products (12 flops each, FMA form) and
-#         4 accurate double-double additions (20 flops each) = 128 flops.
-FLOPS_PER_CFMA = {"fp64": 8, "dd": 128}
+#   DD  : 4 fused double-double multiply-adds t - ab (21 flops each:
+#         exact leading product, fma cross terms, two error-free sums) = 84.
+FLOPS_PER_CFMA = {"fp64": 8, "dd": 84}
 
 
 def kernel_flops(n, tier, algo, dmid):
@@ -55,15 +55,17 @@ def kernel_flops(n, tier, algo, dmid):
 
 
 def schur_node_flops(sp: int, tier: str) -> int:
-    """One include producing a child with sp undecided modes."""
+    """One include producing a child with sp undecided modes (flops: add and
+    multiply 1, fma 2, the hardware reciprocal square root estimate 1)."""
     ent, rows = sp * (2 * sp + 1), 2 * sp
     if tier == "fp64":
-        # entry: 2 FMA; row: mul, FMA, mul; pivot: 2 x (sqrt, div), mul, FMA, 2 mul
-        return 4 * ent + 4 * rows + 9
-    # DD: multiply-subtract = DWTimesDW (12) + AccurateDWPlusDW (20);
-    # row: 2 DD multiplies + 1 multiply-subtract; pivot: 2 DD rsqrt (24 each),
-    # a DD multiply, a multiply-subtract, 2 DD multiplies
-    return 64 * ent + 56 * rows + 116
+        # entry: 2 FMA; row: mul, FMA, mul; pivot: 2 rsqrt (estimate and a
+        # Newton step, 7), mul, FMA, 2 mul for g
+        return 4 * ent + 4 * rows + 19
+    # DD: entry t - ab - cd fused (36); row: 2 DWTimesDW (12 each) and one
+    # fused t - ab (21); pivot: 2 DD rsqrt (29 each), a DWTimesDW, a fused
+    # t - ab, 2 DWTimesDW for g
+    return 36 * ent + 45 * rows + 115
 
 
 def acc_flops(tier: str) -> int:

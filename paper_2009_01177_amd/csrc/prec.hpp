@@ -169,9 +169,25 @@ PREC_HD dd dd_sqrt(dd x) {
   return z;
 }
 
+// Binary64 1/sqrt(a), within about 1.5 ulp.  On the device: the hardware
+// estimate (v_rsq_f64) refined by one Newton step y + y (1 - a y^2) / 2, so
+// the estimate's own error e leaves 1.5 e^2 + 1.5 u; on the host: the library
+// square root and a division.  Not for a <= 0 (the callers test the pivot
+// sign first).
+PREC_HD double rsqrt_d(double a) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double y = __builtin_amdgcn_rsq(a);
+  const double r = a * y;
+  const double h = fma(-r, y, 1.0);
+  return fma(0.5 * y, h, y);
+#else
+  return 1.0 / sqrt(a);
+#endif
+}
+
 // 1/sqrt(x): y1 = y0 + y0 (1 - x y0^2) / 2, x y0^2 in double-double.
 PREC_HD dd dd_rsqrt(dd x) {
-  double y0 = 1.0 / sqrt(x.hi);
+  double y0 = rsqrt_d(x.hi);
   dd y2 = dd_prod_dd(y0, y0);
   dd xy2 = dd_mul(x, y2);
   // h = 1 - xy2; xy2 is within a few ulps of 1, so 1 - xy2.hi is exact.
@@ -182,6 +198,47 @@ PREC_HD dd dd_rsqrt(dd x) {
 }
 
 PREC_HD double dd_to_d(dd a) { return a.hi + a.lo; }
+
+// Fused Schur-complement updates  t - a b  and  t - a b - c d.
+//
+// Composing DWTimesDW and AccurateDWPlusDW costs 29 binary64 operations per
+// product-and-subtract.  These evaluate the whole expression at once: the
+// leading products exactly (two_prod), their cross terms by fma, the
+// leading parts  t.hi - p - q  exactly by a two_sum chain, every low-order
+// piece (t.lo, cross terms, two_sum errors) summed in binary64, and one
+// final two_sum that renormalises.  With u = 2^-53 and inputs normalised
+// (|x.lo| <= u |x.hi|), the absolute error is at most
+//     12 u^2 (|t| + |a b|)               (dd_fms)
+//     22 u^2 (|t| + |a b| + |c d|)       (dd_fms2),
+// against 7 u^2 and 14 u^2 for the composed JMP operations: the same
+// u^2-times-magnitudes form that Cholesky's backward error already has, at
+// 18 and 30 operations.  The dropped a.lo b.lo is part of the bound.
+PREC_HD dd dd_fms(dd t, dd a, dd b) {
+  double p, pe;
+  two_prod(a.hi, b.hi, p, pe);
+  const double x = fma(a.lo, b.hi, fma(a.hi, b.lo, pe));
+  double s, e;
+  two_sum(t.hi, -p, s, e);
+  const double l = (t.lo - x) + e;
+  dd z;
+  two_sum(s, l, z.hi, z.lo);
+  return z;
+}
+
+PREC_HD dd dd_fms2(dd t, dd a, dd b, dd c, dd d) {
+  double p, pe, q, qe;
+  two_prod(a.hi, b.hi, p, pe);
+  two_prod(c.hi, d.hi, q, qe);
+  const double x = fma(a.lo, b.hi, fma(a.hi, b.lo, pe));
+  const double y = fma(c.lo, d.hi, fma(c.hi, d.lo, qe));
+  double s1, e1, s, e2;
+  two_sum(t.hi, -p, s1, e1);
+  two_sum(s1, -q, s, e2);
+  const double l = (((t.lo - x) - y) + e1) + e2;
+  dd z;
+  two_sum(s, l, z.hi, z.lo);
+  return z;
+}
 
 // ---------------------------------------------------------------------------
 // Quad-double

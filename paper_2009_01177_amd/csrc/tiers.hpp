@@ -35,11 +35,15 @@ __device__ __forceinline__ double r_mul(double a, double b) { return a * b; }
 __device__ __forceinline__ double r_neg(double a) { return -a; }
 __device__ __forceinline__ double r_from(double a) { return a; }
 __device__ __forceinline__ double r_lead(double a) { return a; }
-__device__ __forceinline__ double r_rsqrt(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ double r_rsqrt(double a) { return prec::rsqrt_d(a); }
 __device__ __forceinline__ double r_one_minus(double o) { return 1.0 - o; }
 // c - a*b and c + a*b with one rounding
 __device__ __forceinline__ double r_fms(double c, double a, double b) { return fma(-a, b, c); }
 __device__ __forceinline__ double r_fma(double c, double a, double b) { return fma(a, b, c); }
+// t - a*b - c*d (a Schur-update entry)
+__device__ __forceinline__ double r_fms2(double t, double a, double b, double c, double d) {
+  return fma(-c, d, fma(-a, b, t));
+}
 
 __device__ __forceinline__ dd r_add(dd a, dd b) { return prec::dd_add(a, b); }
 __device__ __forceinline__ dd r_sub(dd a, dd b) { return prec::dd_sub(a, b); }
@@ -47,8 +51,9 @@ __device__ __forceinline__ dd r_mul(dd a, dd b) { return prec::dd_mul(a, b); }
 __device__ __forceinline__ dd r_neg(dd a) { return prec::dd_neg(a); }
 __device__ __forceinline__ double r_lead(dd a) { return a.hi; }
 __device__ __forceinline__ dd r_rsqrt(dd a) { return prec::dd_rsqrt(a); }
-__device__ __forceinline__ dd r_fms(dd c, dd a, dd b) { return prec::dd_sub(c, prec::dd_mul(a, b)); }
-__device__ __forceinline__ dd r_fma(dd c, dd a, dd b) { return prec::dd_add(c, prec::dd_mul(a, b)); }
+__device__ __forceinline__ dd r_fms(dd c, dd a, dd b) { return prec::dd_fms(c, a, b); }
+__device__ __forceinline__ dd r_fma(dd c, dd a, dd b) { return prec::dd_fms(c, prec::dd_neg(a), b); }
+__device__ __forceinline__ dd r_fms2(dd t, dd a, dd b, dd c, dd d) { return prec::dd_fms2(t, a, b, c, d); }
 
 __device__ __forceinline__ qd r_add(qd a, qd b) { return prec::qd_add(a, b); }
 __device__ __forceinline__ qd r_sub(qd a, qd b) { return prec::qd_sub(a, b); }
@@ -58,6 +63,7 @@ __device__ __forceinline__ double r_lead(qd a) { return a.x[0]; }
 __device__ __forceinline__ qd r_rsqrt(qd a) { return prec::qd_rsqrt(a); }
 __device__ __forceinline__ qd r_fms(qd c, qd a, qd b) { return prec::qd_sub(c, prec::qd_mul(a, b)); }
 __device__ __forceinline__ qd r_fma(qd c, qd a, qd b) { return prec::qd_add(c, prec::qd_mul(a, b)); }
+__device__ __forceinline__ qd r_fms2(qd t, qd a, qd b, qd c, qd d) { return r_fms(r_fms(t, a, b), c, d); }
 
 template <class R>
 __device__ __forceinline__ R r_zero();

@@ -137,7 +137,7 @@ struct Bottom {
       for (int a = 0; a < 2 * SC; ++a) {
 #pragma unroll
         for (int b = 0; b <= a; ++b) {
-          C[pk(a, b)] = r_fms(r_fms(T[pk(a + O, b + O)], u0[a], u0[b]), u1[a], u1[b]);
+          C[pk(a, b)] = r_fms2(T[pk(a + O, b + O)], u0[a], u0[b], u1[a], u1[b]);
         }
       }
       Bottom<TT, SC>::run(C, gc, m + 1, n, acc, bad);
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void expand_kernel(const typename TT::R* __res
     const int b = e - pk(a, 0);
     const R t = T[pk(a + 2, b + 2)];
     ex[e] = t;
-    in[e] = r_fms(r_fms(t, su0[a], su0[b]), su1[a], su1[b]);
+    in[e] = r_fms2(t, su0[a], su0[b], su1[a], su1[b]);
   }
 }
 
@@ -294,13 +294,34 @@ struct MidSmem {
     }
     return v;
   }
+  // largest work-item count of an LDS phase (entries of all include
+  // children of a level, or their pivot columns)
+  static constexpr int max_items() {
+    int v = 0;
+    for (int j = 0; j + 1 < L; ++j) {
+      const int w = (1 << j) * psize(SM - j - 1);
+      v = v > w ? v : w;
+    }
+    return v;
+  }
   R A[a_vals()];
   R B[b_vals()];
   R gA[32], gB[32];
   R rl0[16], l10[16], rl1[16];
   R u0[u_vals()], u1[u_vals()];
   int32_t mA[32], mB[32];
-  uint16_t pairs[psize(SM)];  // packed index -> (row << 8) | col
+  // packed child index e -> parent offset pk(a+2, b+2) | a << 8 | b << 16
+  uint32_t pairs[psize(SM - 1)];
+};
+
+// Work item idx of a phase with d items per state -> state idx / d, by a
+// multiply and shift: q = (idx * ceil(2^20 / d)) >> 20 is exact while
+// idx * d < 2^20 (the rounding excess of the multiplier is below d).
+struct DivBy {
+  uint32_t m;
+  int d;
+  __device__ explicit DivBy(int d_) : m(((1u << 20) + (uint32_t)d_ - 1u) / (uint32_t)d_), d(d_) {}
+  __device__ int q(int idx) const { return (int)(((uint32_t)idx * m) >> 20); }
 };
 
 template <class TT, int SB>
@@ -313,23 +334,60 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
   using R = typename TT::R;
   using Acc = typename TT::Acc;
   using SMEM = MidSmem<TT, SB>;
+  static_assert(SMEM::max_items() * psize(SMEM::SM) < (1 << 20), "DivBy range");
+  static_assert(psize(SMEM::SM) <= 256, "pairs offsets take 8 bits");
   __shared__ SMEM sm;
   const int lane = threadIdx.x;
-  for (int e = lane; e < psize(SMEM::SM); e += 64) {
+  for (int e = lane; e < psize(SMEM::SM - 1); e += 64) {
     int r = 0;
     while (pk(r + 1, 0) <= e) ++r;
-    sm.pairs[e] = (uint16_t)((r << 8) | (e - pk(r, 0)));
+    const int c = e - pk(r, 0);
+    sm.pairs[e] = (uint32_t)pk(r + 2, c + 2) | ((uint32_t)r << 8) | ((uint32_t)c << 16);
   }
   const int L = s_m - SB;  // middle levels, 0..6
+  const int ps0 = psize(s_m);
   bool bad = false;
 
-  for (int z = blockIdx.x; z < nstates; z += gridDim.x) {
+  // The next state's matrix is fetched into registers while the current
+  // one is expanded: lane k holds entries k, k + 64, ...
+  constexpr int PF = (psize(SMEM::SM) + 63) / 64;
+  static_assert(PF <= 4, "prefetch holds at most four entries per lane");
+  const int f0 = min(lane, ps0 - 1), f1 = min(lane + 64, ps0 - 1);
+  const int f2 = min(lane + 128, ps0 - 1), f3 = min(lane + 192, ps0 - 1);
+  R pf0 = r_zero<R>(), pf1 = pf0, pf2 = pf0, pf3 = pf0;
+  R pg = r_zero<R>();
+  int32_t pm = 0;
+  int z = blockIdx.x;
+  // (indexes past the matrix are clamped to its last entry and not stored)
+  if (z < nstates) {
+    const R* src = mat + (size_t)z * ps0;
+    pf0 = src[f0];
+    if constexpr (PF > 1) pf1 = src[f1];
+    if constexpr (PF > 2) pf2 = src[f2];
+    if constexpr (PF > 3) pf3 = src[f3];
+    pg = gin[z];
+    pm = min_[z];
+  }
+
+  for (; z < nstates; z += gridDim.x) {
     __syncthreads();
-    const R* src = mat + (size_t)z * psize(s_m);
-    for (int e = lane; e < psize(s_m); e += 64) sm.A[e] = src[e];
+    if (lane < ps0) sm.A[lane] = pf0;
+    if constexpr (PF > 1) if (lane + 64 < ps0) sm.A[lane + 64] = pf1;
+    if constexpr (PF > 2) if (lane + 128 < ps0) sm.A[lane + 128] = pf2;
+    if constexpr (PF > 3) if (lane + 192 < ps0) sm.A[lane + 192] = pf3;
     if (lane == 0) {
-      sm.gA[0] = gin[z];
-      sm.mA[0] = min_[z];
+      sm.gA[0] = pg;
+      sm.mA[0] = pm;
+    }
+    const int zn = z + gridDim.x;
+    if (zn < nstates) {
+      const R* src = mat + (size_t)zn * ps0;
+      pf0 = src[f0];
+      if constexpr (PF > 1) pf1 = src[f1];
+      if constexpr (PF > 2) pf2 = src[f2];
+      if constexpr (PF > 3) pf3 = src[f3];
+      pg = gin[zn];
+      pm = min_[zn];
     }
     __syncthreads();
 
@@ -358,23 +416,45 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
         nm[2 * lane + 1] = cm[lane] + 1;
       }
       __syncthreads();
-      for (int idx = lane; idx < ns * rows; idx += 64) {
-        const int zz = idx / rows, a = idx - zz * rows;
-        const R* T = cur + zz * ps;
-        const R u0 = r_mul(T[pk(a + 2, 0)], sm.rl0[zz]);
-        sm.u0[zz * rows + a] = u0;
-        sm.u1[zz * rows + a] = r_mul(r_fms(T[pk(a + 2, 1)], u0, sm.l10[zz]), sm.rl1[zz]);
+      {
+        const DivBy dr(rows);
+        for (int idx = lane; idx < ns * rows; idx += 64) {
+          const int zz = dr.q(idx), a = idx - zz * rows;
+          const R* T = cur + zz * ps;
+          const R u0 = r_mul(T[pk(a + 2, 0)], sm.rl0[zz]);
+          sm.u0[idx] = u0;
+          sm.u1[idx] = r_mul(r_fms(T[pk(a + 2, 1)], u0, sm.l10[zz]), sm.rl1[zz]);
+        }
       }
       __syncthreads();
-      for (int idx = lane; idx < ns * pc; idx += 64) {
-        const int zz = idx / pc, e = idx - zz * pc;
-        const int pr = sm.pairs[e];
-        const int a = pr >> 8, b = pr & 255;
-        const R t = cur[zz * ps + pk(a + 2, b + 2)];
-        const R* u0 = sm.u0 + zz * rows;
-        const R* u1 = sm.u1 + zz * rows;
-        nxt[(2 * zz) * pc + e] = t;
-        nxt[(2 * zz + 1) * pc + e] = r_fms(r_fms(t, u0[a], u0[b]), u1[a], u1[b]);
+      {
+        // two entries per lane per pass, all loads issued before the math
+        const DivBy dc(pc);
+        const int tot = ns * pc;
+        for (int i0 = lane; i0 < tot; i0 += 128) {
+          const int i1 = i0 + 64 < tot ? i0 + 64 : i0;
+          const int z0 = dc.q(i0), e0 = i0 - z0 * pc;
+          const int z1 = dc.q(i1), e1 = i1 - z1 * pc;
+          const uint32_t p0 = sm.pairs[e0], p1 = sm.pairs[e1];
+          const int a0 = (p0 >> 8) & 255, b0 = p0 >> 16;
+          const int a1 = (p1 >> 8) & 255, b1 = p1 >> 16;
+          const R* ua0 = sm.u0 + z0 * rows;
+          const R* ub0 = sm.u1 + z0 * rows;
+          const R* ua1 = sm.u0 + z1 * rows;
+          const R* ub1 = sm.u1 + z1 * rows;
+          const R t0 = cur[z0 * ps + (int)(p0 & 255)];
+          const R t1 = cur[z1 * ps + (int)(p1 & 255)];
+          const R x0 = ua0[a0], y0 = ua0[b0], v0 = ub0[a0], w0 = ub0[b0];
+          const R x1 = ua1[a1], y1 = ua1[b1], v1 = ub1[a1], w1 = ub1[b1];
+          const R c0 = r_fms2(t0, x0, y0, v0, w0);
+          const R c1 = r_fms2(t1, x1, y1, v1, w1);
+          nxt[(2 * z0) * pc + e0] = t0;
+          nxt[(2 * z0 + 1) * pc + e0] = c0;
+          if (i0 + 64 < tot) {
+            nxt[(2 * z1) * pc + e1] = t1;
+            nxt[(2 * z1 + 1) * pc + e1] = c1;
+          }
+        }
       }
       __syncthreads();
       R* t0 = cur; cur = nxt; nxt = t0;
@@ -382,7 +462,9 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
       int32_t* t2 = cm; cm = nm; nm = t2;
     }
 
-    // last middle level: each lane forms its own bottom state in registers
+    // last middle level: each lane forms its own bottom state in registers.
+    // Both children of a state run the same code: the excluded one with
+    // zero pivot multipliers, whose update leaves every entry unchanged.
     LaneAcc<TT> acc;
     acc.t = TT::acc_zero();
     acc.a = TT::acc_zero();
@@ -398,31 +480,25 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
         lm = cm[0];
       } else {
         const int zz = lane >> 1;
+        const bool take = (lane & 1) != 0;
         const R* T = cur + zz * psize(SB + 1);
-        if ((lane & 1) == 0) {
+        const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+        if (take && !pv.ok) bad = true;
+        const R zero = r_zero<R>();
+        const R m0 = take ? pv.rl0 : zero;
+        const R m1 = take ? pv.rl1 : zero;
+        R u0[2 * SB], u1[2 * SB];
 #pragma unroll
-          for (int a = 0; a < 2 * SB; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b) leaf[pk(a, b)] = T[pk(a + 2, b + 2)];
-          lg = cg[zz];
-          lm = cm[zz];
-        } else {
-          const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
-          if (!pv.ok) bad = true;
-          R u0[2 * SB], u1[2 * SB];
-#pragma unroll
-          for (int a = 0; a < 2 * SB; ++a) {
-            u0[a] = r_mul(T[pk(a + 2, 0)], pv.rl0);
-            u1[a] = r_mul(r_fms(T[pk(a + 2, 1)], u0[a], pv.l10), pv.rl1);
-          }
-#pragma unroll
-          for (int a = 0; a < 2 * SB; ++a)
-#pragma unroll
-            for (int b = 0; b <= a; ++b)
-              leaf[pk(a, b)] = r_fms(r_fms(T[pk(a + 2, b + 2)], u0[a], u0[b]), u1[a], u1[b]);
-          lg = r_mul(r_mul(cg[zz], pv.rl0), pv.rl1);
-          lm = cm[zz] + 1;
+        for (int a = 0; a < 2 * SB; ++a) {
+          u0[a] = r_mul(T[pk(a + 2, 0)], m0);
+          u1[a] = r_mul(r_fms(T[pk(a + 2, 1)], u0[a], pv.l10), m1);
         }
+#pragma unroll
+        for (int a = 0; a < 2 * SB; ++a)
+#pragma unroll
+          for (int b = 0; b <= a; ++b) leaf[pk(a, b)] = r_fms2(T[pk(a + 2, b + 2)], u0[a], u0[b], u1[a], u1[b]);
+        lg = take ? r_mul(r_mul(cg[zz], pv.rl0), pv.rl1) : cg[zz];
+        lm = cm[zz] + (take ? 1 : 0);
       }
       Bottom<TT, SB>::run(leaf, lg, lm, n, acc, bad);
     }
