@@ -71,7 +71,9 @@ PREC_HD void two_prod(double a, double b, double& p, double& e) {
 // Double-double
 // ---------------------------------------------------------------------------
 
-struct dd {
+// 16-byte aligned, so that a value moves through LDS and memory as one
+// 128-bit access
+struct alignas(16) dd {
   double hi, lo;
 };
 
@@ -244,7 +246,7 @@ PREC_HD dd dd_fms2(dd t, dd a, dd b, dd c, dd d) {
 // Quad-double
 // ---------------------------------------------------------------------------
 
-struct qd {
+struct alignas(16) qd {
   double x[4];
 };
 

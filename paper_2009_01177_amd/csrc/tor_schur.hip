@@ -48,6 +48,10 @@ namespace tor {
 __host__ __device__ constexpr int pk(int a, int b) { return a * (a + 1) / 2 + b; }
 // Entries of the packed 2s x 2s symmetric matrix of s modes.
 __host__ __device__ constexpr int psize(int s) { return s * (2 * s + 1); }
+// Distance between consecutive states (or pivot columns) in LDS: rounded up
+// to an odd number of values, so that lanes reading the same entry of
+// different states hit different banks.
+__host__ __device__ constexpr int odd_up(int v) { return v | 1; }
 
 // --------------------------------------------------------------------------
 // Real-tier arithmetic helpers
@@ -104,6 +108,34 @@ __device__ __forceinline__ Pivot<R> make_pivot(const R& p00, const R& p10, const
   return p;
 }
 
+// det of the 2x2 pivot block, p00 p11 - p10^2 (one rounding in F64; the
+// fused form in DD).  Its relative error is of the order of the block's
+// condition times u, the same as that of the Cholesky pivot p11 - l10^2.
+__device__ __forceinline__ double r_det2(double p00, double p10, double p11) {
+  return fma(p00, p11, -(p10 * p10));
+}
+__device__ __forceinline__ dd r_det2(const dd& p00, const dd& p10, const dd& p11) {
+  return prec::dd_fms2(dd{0.0, 0.0}, prec::dd_neg(p00), p11, p10, p10);
+}
+__device__ __forceinline__ qd r_det2(const qd& p00, const qd& p10, const qd& p11) {
+  return r_fms(r_mul(p00, p11), p10, p10);
+}
+
+// The same pivot from det(P) = p00 p11 - p10^2: rl1 = p00 rl0 rd with
+// rd = det(P)^(-1/2), so the two reciprocal square roots are independent;
+// the child's g is g rd.
+template <class R>
+__device__ __forceinline__ Pivot<R> make_pivot_det(const R& p00, const R& p10, const R& p11, R& rd) {
+  Pivot<R> p;
+  const R det = r_det2(p00, p10, p11);
+  p.ok = r_lead(p00) > 0.0 && r_lead(det) > 0.0;
+  p.rl0 = r_rsqrt(p00);
+  rd = r_rsqrt(det);
+  p.l10 = r_mul(p10, p.rl0);
+  p.rl1 = r_mul(r_mul(p00, p.rl0), rd);
+  return p;
+}
+
 // --------------------------------------------------------------------------
 // Bottom level: one lane, all subsets of S modes, registers only.
 // T is the packed 2S x 2S matrix of the lane's state, g its det^(-1/2),
@@ -120,12 +152,16 @@ struct Bottom {
                                                LaneAcc<TT>& acc, bool& bad) {
     constexpr int SC = S - 1 - I;
     constexpr int O = 2 * I + 2;
-    const Pivot<R> pv = make_pivot(T[pk(2 * I, 2 * I)], T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
-    if (!pv.ok) bad = true;
-    const R gc = r_mul(r_mul(g, pv.rl0), pv.rl1);
     if constexpr (SC == 0) {
-      emit_term(acc, gc, m + 1, n);
+      // the last mode: only the term is needed, g det(P)^(-1/2)
+      const R& p00 = T[pk(2 * I, 2 * I)];
+      const R det = r_det2(p00, T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
+      if (!(r_lead(p00) > 0.0 && r_lead(det) > 0.0)) bad = true;
+      emit_term(acc, r_mul(g, r_rsqrt(det)), m + 1, n);
     } else {
+      const Pivot<R> pv = make_pivot(T[pk(2 * I, 2 * I)], T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
+      if (!pv.ok) bad = true;
+      const R gc = r_mul(r_mul(g, pv.rl0), pv.rl1);
       R u0[2 * SC], u1[2 * SC];
 #pragma unroll
       for (int a = 0; a < 2 * SC; ++a) {
@@ -268,13 +304,84 @@ __global__ __launch_bounds__(256) void expand_kernel(const typename TT::R* __res
 // follows.  L = s_m - s_b <= 6 middle levels give up to 64 bottom states.
 // --------------------------------------------------------------------------
 
+// Work item idx of a phase with d items per state -> state idx / d, by a
+// multiply and shift: q = (idx * ceil(2^20 / d)) >> 20 is exact while
+// idx * d < 2^20 (the rounding excess of the multiplier is below d).
+struct DivBy {
+  uint32_t m;
+  int d;
+  __device__ explicit DivBy(int d_) : m(((1u << 20) + (uint32_t)d_ - 1u) / (uint32_t)d_), d(d_) {}
+  __device__ int q(int idx) const { return (int)(((uint32_t)idx * m) >> 20); }
+};
+
+// One pass of a middle-level expansion over KK * 64 work items starting at
+// base: item (state z, child mode block (bi, bj)) computes rows 2bi, 2bi+1
+// and columns 2bj, 2bj+1 of both children of z, every load issued before
+// the math.  Items past tot repeat the last valid one and are not stored;
+// the upper entry of a diagonal block is computed from its mirror and not
+// stored.
+template <class R, int KK>
+__device__ __forceinline__ void entry_pass(int base, int lane, int tot, const DivBy& db,
+                                           const uint16_t* blocks, const R* cur, int ps,
+                                           const R* u, int urs, R* nxt, int pcs) {
+  int zk[KK], rk[KK], ck[KK];
+  bool dg[KK];
+  R t00[KK], t01[KK], t10[KK], t11[KK], ua[KK][4], ub[KK][4];
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    const int i = min(base + lane + 64 * k, tot - 1);
+    zk[k] = db.q(i);
+    const uint32_t bp = blocks[i - zk[k] * db.d];
+    rk[k] = 2 * (int)(bp & 255u);
+    ck[k] = 2 * (int)(bp >> 8);
+    dg[k] = rk[k] == ck[k];
+  }
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    const R* T = cur + zk[k] * ps;
+    const int p0 = pk(rk[k] + 2, ck[k] + 2), p1 = pk(rk[k] + 3, ck[k] + 2);
+    t00[k] = T[p0];
+    t01[k] = T[dg[k] ? p1 : p0 + 1];
+    t10[k] = T[p1];
+    t11[k] = T[p1 + 1];
+    const R* U = u + zk[k] * urs;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      ua[k][v] = U[2 * rk[k] + v];
+      ub[k][v] = U[2 * ck[k] + v];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KK; ++k) {
+    const R c00 = r_fms2(t00[k], ua[k][0], ub[k][0], ua[k][1], ub[k][1]);
+    const R c01 = r_fms2(t01[k], ua[k][0], ub[k][2], ua[k][1], ub[k][3]);
+    const R c10 = r_fms2(t10[k], ua[k][2], ub[k][0], ua[k][3], ub[k][1]);
+    const R c11 = r_fms2(t11[k], ua[k][2], ub[k][2], ua[k][3], ub[k][3]);
+    if (base + lane + 64 * k < tot) {
+      R* X = nxt + (2 * zk[k]) * pcs;  // leaves the mode out
+      R* Y = X + pcs;                   // takes it in
+      const int q0 = pk(rk[k], ck[k]), q1 = pk(rk[k] + 1, ck[k]);
+      X[q0] = t00[k];
+      Y[q0] = c00;
+      X[q1] = t10[k];
+      Y[q1] = c10;
+      X[q1 + 1] = t11[k];
+      Y[q1 + 1] = c11;
+      if (!dg[k]) {
+        X[q0 + 1] = t01[k];
+        Y[q0 + 1] = c01;
+      }
+    }
+  }
+}
+
 template <class TT, int SB>
 struct MidSmem {
   using R = typename TT::R;
   static constexpr int L = 6;
   static constexpr int SM = SB + L;
   // level j (s = SM - j modes, 2^j states): even levels in A, odd in B
-  static constexpr int level_vals(int j) { return (1 << j) * psize(SM - j); }
+  static constexpr int level_vals(int j) { return (1 << j) * odd_up(psize(SM - j)); }
   static constexpr int a_vals() {
     int v = 0;
     for (int j = 0; j < L; j += 2) v = v > level_vals(j) ? v : level_vals(j);
@@ -285,11 +392,12 @@ struct MidSmem {
     for (int j = 1; j < L; j += 2) v = v > level_vals(j) ? v : level_vals(j);
     return v;
   }
-  // pivot columns of the LDS expansions (levels 0 .. L-2)
+  // pivot columns of the LDS expansions (levels 0 .. L-2): per state, the
+  // pair (u0, u1) of every row below the pivot block
   static constexpr int u_vals() {
     int v = 0;
     for (int j = 0; j + 1 < L; ++j) {
-      const int w = (1 << j) * 2 * (SM - j - 1);
+      const int w = (1 << j) * odd_up(4 * (SM - j - 1));
       v = v > w ? v : w;
     }
     return v;
@@ -307,21 +415,10 @@ struct MidSmem {
   R A[a_vals()];
   R B[b_vals()];
   R gA[32], gB[32];
-  R rl0[16], l10[16], rl1[16];
-  R u0[u_vals()], u1[u_vals()];
+  R u[u_vals()];
   int32_t mA[32], mB[32];
-  // packed child index e -> parent offset pk(a+2, b+2) | a << 8 | b << 16
-  uint32_t pairs[psize(SM - 1)];
-};
-
-// Work item idx of a phase with d items per state -> state idx / d, by a
-// multiply and shift: q = (idx * ceil(2^20 / d)) >> 20 is exact while
-// idx * d < 2^20 (the rounding excess of the multiplier is below d).
-struct DivBy {
-  uint32_t m;
-  int d;
-  __device__ explicit DivBy(int d_) : m(((1u << 20) + (uint32_t)d_ - 1u) / (uint32_t)d_), d(d_) {}
-  __device__ int q(int idx) const { return (int)(((uint32_t)idx * m) >> 20); }
+  // mode block index q of a child -> (i, j), i >= j, as i | j << 8
+  uint16_t blocks[(SM - 1) * SM / 2];
 };
 
 template <class TT, int SB>
@@ -335,14 +432,12 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
   using Acc = typename TT::Acc;
   using SMEM = MidSmem<TT, SB>;
   static_assert(SMEM::max_items() * psize(SMEM::SM) < (1 << 20), "DivBy range");
-  static_assert(psize(SMEM::SM) <= 256, "pairs offsets take 8 bits");
   __shared__ SMEM sm;
   const int lane = threadIdx.x;
-  for (int e = lane; e < psize(SMEM::SM - 1); e += 64) {
-    int r = 0;
-    while (pk(r + 1, 0) <= e) ++r;
-    const int c = e - pk(r, 0);
-    sm.pairs[e] = (uint32_t)pk(r + 2, c + 2) | ((uint32_t)r << 8) | ((uint32_t)c << 16);
+  for (int q = lane; q < (SMEM::SM - 1) * SMEM::SM / 2; q += 64) {
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= q) ++i;
+    sm.blocks[q] = (uint16_t)(i | ((q - i * (i + 1) / 2) << 8));
   }
   const int L = s_m - SB;  // middle levels, 0..6
   const int ps0 = psize(s_m);
@@ -401,60 +496,54 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
     for (int j = 0; j + 1 < L; ++j) {
       const int S = s_m - j;  // modes of level j
       const int ns = 1 << j;
-      const int ps = psize(S), pc = psize(S - 1);
-      const int rows = 2 * (S - 1);
-      if (lane < ns) {
-        const R* T = cur + lane * ps;
-        const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
-        if (!pv.ok) bad = true;
-        sm.rl0[lane] = pv.rl0;
-        sm.l10[lane] = pv.l10;
-        sm.rl1[lane] = pv.rl1;
-        ng[2 * lane] = cg[lane];
-        nm[2 * lane] = cm[lane];
-        ng[2 * lane + 1] = r_mul(r_mul(cg[lane], pv.rl0), pv.rl1);
-        nm[2 * lane + 1] = cm[lane] + 1;
-      }
-      __syncthreads();
+      const int ps = odd_up(psize(S));      // state stride of level j
+      const int pcs = odd_up(psize(S - 1)); // state stride of level j + 1
+      const int urs = odd_up(4 * (S - 1));  // pivot-column stride
       {
-        const DivBy dr(rows);
-        for (int idx = lane; idx < ns * rows; idx += 64) {
-          const int zz = dr.q(idx), a = idx - zz * rows;
+        // pivot columns, one mode (two rows) per item; every item forms its
+        // state's pivot itself (in the determinant form, whose chain of
+        // dependent operations is about half that of rsqrt(p00) -> l10 ->
+        // p11 - l10^2 -> rsqrt), and the first item of a state also the
+        // children's g and |Z|
+        const int nmo = S - 1;
+        const DivBy dm(nmo);
+        for (int idx = lane; idx < ns * nmo; idx += 64) {
+          const int zz = dm.q(idx), i = idx - zz * nmo;
           const R* T = cur + zz * ps;
-          const R u0 = r_mul(T[pk(a + 2, 0)], sm.rl0[zz]);
-          sm.u0[idx] = u0;
-          sm.u1[idx] = r_mul(r_fms(T[pk(a + 2, 1)], u0, sm.l10[zz]), sm.rl1[zz]);
-        }
-      }
-      __syncthreads();
-      {
-        // two entries per lane per pass, all loads issued before the math
-        const DivBy dc(pc);
-        const int tot = ns * pc;
-        for (int i0 = lane; i0 < tot; i0 += 128) {
-          const int i1 = i0 + 64 < tot ? i0 + 64 : i0;
-          const int z0 = dc.q(i0), e0 = i0 - z0 * pc;
-          const int z1 = dc.q(i1), e1 = i1 - z1 * pc;
-          const uint32_t p0 = sm.pairs[e0], p1 = sm.pairs[e1];
-          const int a0 = (p0 >> 8) & 255, b0 = p0 >> 16;
-          const int a1 = (p1 >> 8) & 255, b1 = p1 >> 16;
-          const R* ua0 = sm.u0 + z0 * rows;
-          const R* ub0 = sm.u1 + z0 * rows;
-          const R* ua1 = sm.u0 + z1 * rows;
-          const R* ub1 = sm.u1 + z1 * rows;
-          const R t0 = cur[z0 * ps + (int)(p0 & 255)];
-          const R t1 = cur[z1 * ps + (int)(p1 & 255)];
-          const R x0 = ua0[a0], y0 = ua0[b0], v0 = ub0[a0], w0 = ub0[b0];
-          const R x1 = ua1[a1], y1 = ua1[b1], v1 = ub1[a1], w1 = ub1[b1];
-          const R c0 = r_fms2(t0, x0, y0, v0, w0);
-          const R c1 = r_fms2(t1, x1, y1, v1, w1);
-          nxt[(2 * z0) * pc + e0] = t0;
-          nxt[(2 * z0 + 1) * pc + e0] = c0;
-          if (i0 + 64 < tot) {
-            nxt[(2 * z1) * pc + e1] = t1;
-            nxt[(2 * z1 + 1) * pc + e1] = c1;
+          const int r = 2 * i + 2;
+          const R a0 = T[pk(r, 0)], a1 = T[pk(r, 1)];
+          const R b0 = T[pk(r + 1, 0)], b1 = T[pk(r + 1, 1)];
+          R rd;
+          const Pivot<R> pv = make_pivot_det(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)], rd);
+          if (!pv.ok) bad = true;
+          const R u0a = r_mul(a0, pv.rl0), u0b = r_mul(b0, pv.rl0);
+          R* U = sm.u + zz * urs + 4 * i;
+          U[0] = u0a;
+          U[1] = r_mul(r_fms(a1, u0a, pv.l10), pv.rl1);
+          U[2] = u0b;
+          U[3] = r_mul(r_fms(b1, u0b, pv.l10), pv.rl1);
+          if (i == 0) {
+            ng[2 * zz] = cg[zz];
+            nm[2 * zz] = cm[zz];
+            ng[2 * zz + 1] = r_mul(cg[zz], rd);
+            nm[2 * zz + 1] = cm[zz] + 1;
           }
         }
+      }
+      __syncthreads();
+      {
+        // children, in passes of K * 64 mode blocks; the last, partial pass
+        // uses only as many 64-item slices as it needs
+        constexpr int K = sizeof(R) == sizeof(double) ? 4 : 2;
+        const int S1 = S - 1;
+        const DivBy db(S1 * (S1 + 1) / 2);
+        const int tot = ns * db.d;
+        int base = 0;
+        for (; base + 64 * K <= tot; base += 64 * K)
+          entry_pass<R, K>(base, lane, tot, db, sm.blocks, cur, ps, sm.u, urs, nxt, pcs);
+        for (; tot - base > 64; base += 128)
+          entry_pass<R, 2>(base, lane, tot, db, sm.blocks, cur, ps, sm.u, urs, nxt, pcs);
+        if (tot - base > 0) entry_pass<R, 1>(base, lane, tot, db, sm.blocks, cur, ps, sm.u, urs, nxt, pcs);
       }
       __syncthreads();
       R* t0 = cur; cur = nxt; nxt = t0;
@@ -481,7 +570,7 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
       } else {
         const int zz = lane >> 1;
         const bool take = (lane & 1) != 0;
-        const R* T = cur + zz * psize(SB + 1);
+        const R* T = cur + zz * odd_up(psize(SB + 1));
         const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
         if (take && !pv.ok) bad = true;
         const R zero = r_zero<R>();
