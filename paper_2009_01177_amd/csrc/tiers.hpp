@@ -172,6 +172,39 @@ __device__ __forceinline__ qd lane_xor(qd x, int m) {
   return qd{{lane_xor(x.x[0], m), lane_xor(x.x[1], m), lane_xor(x.x[2], m), lane_xor(x.x[3], m)}};
 }
 
+// DPP moves within rows of 16 lanes; every lane has a source, so no bound
+// control is needed.  CTRL: 0xB1 quad_perm [1,0,3,2], 0x4E quad_perm
+// [2,3,0,1], 0x141 row_half_mirror, 0x140 row_mirror.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ dd dpp_mov(dd x) {
+  return dd{dpp_mov<CTRL>(x.hi), dpp_mov<CTRL>(x.lo)};
+}
+template <int CTRL>
+__device__ __forceinline__ qd dpp_mov(qd x) {
+  return qd{{dpp_mov<CTRL>(x.x[0]), dpp_mov<CTRL>(x.x[1]), dpp_mov<CTRL>(x.x[2]), dpp_mov<CTRL>(x.x[3])}};
+}
+
+// Total over the 64 lanes in a fixed order: pairs, quads, groups of 8 and
+// rows of 16 by DPP moves, then the four row totals read from lanes 0, 16,
+// 32 and 48 and added as (r0 + r1) + (r2 + r3).  Every lane returns the same
+// value.
+template <class TT>
+__device__ __forceinline__ typename TT::Acc wave_total(typename TT::Acc v) {
+  v = TT::acc_merge(v, dpp_mov<0xB1>(v));
+  v = TT::acc_merge(v, dpp_mov<0x4E>(v));
+  v = TT::acc_merge(v, dpp_mov<0x141>(v));
+  v = TT::acc_merge(v, dpp_mov<0x140>(v));
+  const typename TT::Acc r0 = lane_bcast(v, 0), r1 = lane_bcast(v, 16);
+  const typename TT::Acc r2 = lane_bcast(v, 32), r3 = lane_bcast(v, 48);
+  return TT::acc_merge(TT::acc_merge(r0, r1), TT::acc_merge(r2, r3));
+}
+
 // Sum over the 64 lanes in a fixed butterfly order; every lane gets the sum.
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {

@@ -421,77 +421,62 @@ struct MidSmem {
   uint16_t blocks[(SM - 1) * SM / 2];
 };
 
+// Orders one wavefront's LDS accesses across its lanes: the compiler keeps
+// memory accesses on their side, and the wave waits for its outstanding LDS
+// operations.  (A wavefront's LDS operations complete in issue order.)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The pieces of the middle + bottom kernel, for one wavefront.
 template <class TT, int SB>
-__global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restrict__ mat,
-                                                  const typename TT::R* __restrict__ gin,
-                                                  const int32_t* __restrict__ min_, int s_m,
-                                                  int nstates, int n,
-                                                  typename TT::Acc* __restrict__ partials,
-                                                  int32_t* __restrict__ status) {
+struct Leaf {
   using R = typename TT::R;
   using Acc = typename TT::Acc;
   using SMEM = MidSmem<TT, SB>;
-  static_assert(SMEM::max_items() * psize(SMEM::SM) < (1 << 20), "DivBy range");
-  __shared__ SMEM sm;
-  const int lane = threadIdx.x;
-  for (int q = lane; q < (SMEM::SM - 1) * SMEM::SM / 2; q += 64) {
-    int i = 0;
-    while ((i + 1) * (i + 2) / 2 <= q) ++i;
-    sm.blocks[q] = (uint16_t)(i | ((q - i * (i + 1) / 2) << 8));
-  }
-  const int L = s_m - SB;  // middle levels, 0..6
-  const int ps0 = psize(s_m);
-  bool bad = false;
-
-  // The next state's matrix is fetched into registers while the current
-  // one is expanded: lane k holds entries k, k + 64, ...
-  constexpr int PF = (psize(SMEM::SM) + 63) / 64;
+  static constexpr int NP = psize(SB + 1);
+  // The next state's matrix is fetched into registers while the current one
+  // is expanded: lane k holds entries k, k + 64, ... (indexes past the
+  // matrix are clamped to its last entry and not stored).
+  static constexpr int PF = (psize(SMEM::SM) + 63) / 64;
   static_assert(PF <= 4, "prefetch holds at most four entries per lane");
-  const int f0 = min(lane, ps0 - 1), f1 = min(lane + 64, ps0 - 1);
-  const int f2 = min(lane + 128, ps0 - 1), f3 = min(lane + 192, ps0 - 1);
-  R pf0 = r_zero<R>(), pf1 = pf0, pf2 = pf0, pf3 = pf0;
-  R pg = r_zero<R>();
-  int32_t pm = 0;
-  int z = blockIdx.x;
-  // (indexes past the matrix are clamped to its last entry and not stored)
-  if (z < nstates) {
+
+  __device__ __forceinline__ static void fetch(const R* mat, const R* gin, const int32_t* min_, int z,
+                                               int ps0, int lane, R& v0, R& v1, R& v2, R& v3, R& g,
+                                               int32_t& m) {
     const R* src = mat + (size_t)z * ps0;
-    pf0 = src[f0];
-    if constexpr (PF > 1) pf1 = src[f1];
-    if constexpr (PF > 2) pf2 = src[f2];
-    if constexpr (PF > 3) pf3 = src[f3];
-    pg = gin[z];
-    pm = min_[z];
+    v0 = src[min(lane, ps0 - 1)];
+    if constexpr (PF > 1) v1 = src[min(lane + 64, ps0 - 1)];
+    if constexpr (PF > 2) v2 = src[min(lane + 128, ps0 - 1)];
+    if constexpr (PF > 3) v3 = src[min(lane + 192, ps0 - 1)];
+    g = gin[z];
+    m = min_[z];
   }
 
-  for (; z < nstates; z += gridDim.x) {
-    __syncthreads();
-    if (lane < ps0) sm.A[lane] = pf0;
-    if constexpr (PF > 1) if (lane + 64 < ps0) sm.A[lane + 64] = pf1;
-    if constexpr (PF > 2) if (lane + 128 < ps0) sm.A[lane + 128] = pf2;
-    if constexpr (PF > 3) if (lane + 192 < ps0) sm.A[lane + 192] = pf3;
+  __device__ __forceinline__ static void store(SMEM& sm, int ps0, int lane, const R& v0, const R& v1,
+                                               const R& v2, const R& v3, const R& g, int32_t m) {
+    if (lane < ps0) sm.A[lane] = v0;
+    if constexpr (PF > 1) if (lane + 64 < ps0) sm.A[lane + 64] = v1;
+    if constexpr (PF > 2) if (lane + 128 < ps0) sm.A[lane + 128] = v2;
+    if constexpr (PF > 3) if (lane + 192 < ps0) sm.A[lane + 192] = v3;
     if (lane == 0) {
-      sm.gA[0] = pg;
-      sm.mA[0] = pm;
+      sm.gA[0] = g;
+      sm.mA[0] = m;
     }
-    const int zn = z + gridDim.x;
-    if (zn < nstates) {
-      const R* src = mat + (size_t)zn * ps0;
-      pf0 = src[f0];
-      if constexpr (PF > 1) pf1 = src[f1];
-      if constexpr (PF > 2) pf2 = src[f2];
-      if constexpr (PF > 3) pf3 = src[f3];
-      pg = gin[zn];
-      pm = min_[zn];
-    }
-    __syncthreads();
+  }
 
-    // levels 0 .. L-1 in LDS
-    R* cur = sm.A;
+  // Levels 0 .. L-2 of the state in sm.A, breadth-first in LDS; on return
+  // cur, cg, cm hold level L-1.
+  __device__ __forceinline__ static void middle(SMEM& sm, int s_m, int L, int lane, bool& bad, R*& cur,
+                                                R*& cg, int32_t*& cm) {
+    cur = sm.A;
     R* nxt = sm.B;
-    R* cg = sm.gA;
+    cg = sm.gA;
     R* ng = sm.gB;
-    int32_t* cm = sm.mA;
+    cm = sm.mA;
     int32_t* nm = sm.mB;
     for (int j = 0; j + 1 < L; ++j) {
       const int S = s_m - j;  // modes of level j
@@ -530,7 +515,7 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
           }
         }
       }
-      __syncthreads();
+      wave_sync();
       {
         // children, in passes of K * 64 mode blocks; the last, partial pass
         // uses only as many 64-item slices as it needs
@@ -545,64 +530,141 @@ __global__ __launch_bounds__(64) void leaf_kernel(const typename TT::R* __restri
           entry_pass<R, 2>(base, lane, tot, db, sm.blocks, cur, ps, sm.u, urs, nxt, pcs);
         if (tot - base > 0) entry_pass<R, 1>(base, lane, tot, db, sm.blocks, cur, ps, sm.u, urs, nxt, pcs);
       }
-      __syncthreads();
+      wave_sync();
       R* t0 = cur; cur = nxt; nxt = t0;
       R* t1 = cg; cg = ng; ng = t1;
       int32_t* t2 = cm; cm = nm; nm = t2;
     }
+  }
 
-    // last middle level: each lane forms its own bottom state in registers.
-    // Both children of a state run the same code: the excluded one with
-    // zero pivot multipliers, whose update leaves every entry unchanged.
+  // Expand state z (its matrix prefetched in v0..v3, g, m) through the
+  // middle levels; each lane then forms its own bottom state (leaf, lg,
+  // lm) from its pair of the last middle level, in registers: both children
+  // run the same code, the excluded one with zero pivot multipliers, whose
+  // update leaves every entry unchanged (lane 0 takes the whole state when
+  // L == 0; lanes without a state compute on state 0 and are not used).
+  // Then fetch the wave's next state zn.
+  __device__ __forceinline__ static void expand(SMEM& sm, const R* mat, const R* gin, const int32_t* min_,
+                                                int zn, int nstates, int s_m, int L, int ps0, int lane,
+                                                bool& bad, R& v0, R& v1, R& v2, R& v3, R& g, int32_t& m,
+                                                R (&leaf)[psize(SB)], R& lg, int32_t& lm) {
+    store(sm, ps0, lane, v0, v1, v2, v3, g, m);
+    if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, g, m);
+    wave_sync();
+    R* cur;
+    R* cg;
+    int32_t* cm;
+    middle(sm, s_m, L, lane, bad, cur, cg, cm);
+    if (L == 0) {
+#pragma unroll
+      for (int e = 0; e < psize(SB); ++e) leaf[e] = cur[e];
+      lg = cg[0];
+      lm = cm[0];
+      return;
+    }
+    const int zz = lane < (1 << L) ? lane >> 1 : 0;
+    const bool inc = (lane & 1) != 0;
+    const R* T = cur + zz * odd_up(psize(SB + 1));
+    const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+    if (inc && lane < (1 << L) && !pv.ok) bad = true;
+    const R zero = r_zero<R>();
+    const R m0 = inc ? pv.rl0 : zero;
+    const R m1 = inc ? pv.rl1 : zero;
+    R u0[2 * SB], u1[2 * SB];
+#pragma unroll
+    for (int a = 0; a < 2 * SB; ++a) {
+      u0[a] = r_mul(T[pk(a + 2, 0)], m0);
+      u1[a] = r_mul(r_fms(T[pk(a + 2, 1)], u0[a], pv.l10), m1);
+    }
+#pragma unroll
+    for (int a = 0; a < 2 * SB; ++a)
+#pragma unroll
+      for (int b = 0; b <= a; ++b) leaf[pk(a, b)] = r_fms2(T[pk(a + 2, b + 2)], u0[a], u0[b], u1[a], u1[b]);
+    lg = inc ? r_mul(r_mul(cg[zz], pv.rl0), pv.rl1) : cg[zz];
+    lm = cm[zz] + (inc ? 1 : 0);
+  }
+
+  // The bottom of the lane's state and the wave's fixed-order totals,
+  // stored as state z's partial.
+  __device__ __forceinline__ static void finish(const R (&leaf)[psize(SB)], const R& lg, int32_t lm, int L,
+                                                int lane, int n, int z, Acc* partials, bool& bad) {
     LaneAcc<TT> acc;
     acc.t = TT::acc_zero();
     acc.a = TT::acc_zero();
-    const int nleaves = 1 << L;
-    if (lane < nleaves) {
-      R leaf[psize(SB)];
-      R lg;
-      int lm;
-      if (L == 0) {
-#pragma unroll
-        for (int e = 0; e < psize(SB); ++e) leaf[e] = cur[e];
-        lg = cg[0];
-        lm = cm[0];
-      } else {
-        const int zz = lane >> 1;
-        const bool take = (lane & 1) != 0;
-        const R* T = cur + zz * odd_up(psize(SB + 1));
-        const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
-        if (take && !pv.ok) bad = true;
-        const R zero = r_zero<R>();
-        const R m0 = take ? pv.rl0 : zero;
-        const R m1 = take ? pv.rl1 : zero;
-        R u0[2 * SB], u1[2 * SB];
-#pragma unroll
-        for (int a = 0; a < 2 * SB; ++a) {
-          u0[a] = r_mul(T[pk(a + 2, 0)], m0);
-          u1[a] = r_mul(r_fms(T[pk(a + 2, 1)], u0[a], pv.l10), m1);
-        }
-#pragma unroll
-        for (int a = 0; a < 2 * SB; ++a)
-#pragma unroll
-          for (int b = 0; b <= a; ++b) leaf[pk(a, b)] = r_fms2(T[pk(a + 2, b + 2)], u0[a], u0[b], u1[a], u1[b]);
-        lg = take ? r_mul(r_mul(cg[zz], pv.rl0), pv.rl1) : cg[zz];
-        lm = cm[zz] + (take ? 1 : 0);
-      }
-      Bottom<TT, SB>::run(leaf, lg, lm, n, acc, bad);
-    }
-    // fixed-order butterfly over the wave, then one partial per state
-    Acc t = acc.t, a = acc.a;
-#pragma unroll
-    for (int msk = 32; msk >= 1; msk >>= 1) {
-      t = TT::acc_merge(t, lane_xor(t, msk));
-      a = TT::acc_merge(a, lane_xor(a, msk));
-    }
+    if (lane < (1 << L)) Bottom<TT, SB>::run(leaf, lg, lm, n, acc, bad);
+    const Acc tt = wave_total<TT>(acc.t);
+    const Acc ta = wave_total<TT>(acc.a);
     if (lane == 0) {
-      partials[(size_t)z * 2] = t;
-      partials[(size_t)z * 2 + 1] = a;
+      partials[(size_t)z * 2] = tt;
+      partials[(size_t)z * 2 + 1] = ta;
     }
   }
+};
+
+// Middle + bottom kernel.  W = 1: one wavefront per workgroup expands its
+// states one after another.  W = 2: the two wavefronts of a workgroup take
+// turns with the workgroup's LDS: while one expands a state's middle levels
+// (bound by LDS and dependency latency) down to its lanes' bottom states in
+// registers, the other runs the bottom of the state it expanded before
+// (register arithmetic only).  Wavefront w takes states W * blockIdx.x + w + t * W *
+// gridDim.x, t = 0, 1, ...
+// Wavefronts per SIMD the register allocation aims at: two for the
+// two-wavefront kernel where its registers allow (all but double-double with
+// a four-mode bottom), else one.
+template <class TT, int SB, int W>
+constexpr int leaf_waves_per_simd() {
+  return (W == 2 && !(TT::id == TOR_DD && SB >= 4)) ? 2 : 1;
+}
+
+template <class TT, int SB, int W>
+__global__ __launch_bounds__(64 * W)
+__attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf_kernel(const typename TT::R* __restrict__ mat,
+                                                      const typename TT::R* __restrict__ gin,
+                                                      const int32_t* __restrict__ min_, int s_m,
+                                                      int nstates, int n,
+                                                      typename TT::Acc* __restrict__ partials,
+                                                      int32_t* __restrict__ status) {
+  using R = typename TT::R;
+  using LF = Leaf<TT, SB>;
+  using SMEM = typename LF::SMEM;
+  static_assert(SMEM::max_items() * psize(SMEM::SM) < (1 << 20), "DivBy range");
+  static_assert(W == 1 || W == 2, "one or two wavefronts");
+  __shared__ SMEM sm;
+  const int wv = (int)threadIdx.x >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  for (int q = (int)threadIdx.x; q < (SMEM::SM - 1) * SMEM::SM / 2; q += 64 * W) {
+    int i = 0;
+    while ((i + 1) * (i + 2) / 2 <= q) ++i;
+    sm.blocks[q] = (uint16_t)(i | ((q - i * (i + 1) / 2) << 8));
+  }
+  __syncthreads();
+  const int L = s_m - SB;  // middle levels, 0..6
+  const int ps0 = psize(s_m);
+  const int zstride = W * (int)gridDim.x;
+  bool bad = false;
+  R v0 = r_zero<R>(), v1 = v0, v2 = v0, v3 = v0, g = v0, lg = v0;
+  int32_t m = 0, lm = 0;
+  R leaf[psize(SB)];
+
+  const int zb = W * (int)blockIdx.x;
+  if (zb + wv < nstates) LF::fetch(mat, gin, min_, zb + wv, ps0, lane, v0, v1, v2, v3, g, m);
+  // W = 2: both wavefronts run the same loop, expand | barrier | bottom |
+  // barrier, with wavefront 1 one barrier behind: barrier k of one pairs
+  // with barrier k of the other, so each expansion starts after the other
+  // wavefront's expansion has ended and its bottom overlaps the other's
+  // expansion.  Both run 2 * rounds + 1 barriers.
+  const int rounds = zb < nstates ? (nstates - zb + zstride - 1) / zstride : 0;
+  if (W == 2 && wv == 1) __syncthreads();
+  for (int t = 0; t < rounds; ++t) {
+    const int z = zb + wv + t * zstride;
+    if (z < nstates)
+      LF::expand(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, g, m,
+                 leaf, lg, lm);
+    if (W == 2) __syncthreads(); else wave_sync();
+    if (z < nstates) LF::finish(leaf, lg, lm, L, lane, n, z, partials, bad);
+    if (W == 2) __syncthreads();
+  }
+  if (W == 2 && wv == 0) __syncthreads();
   if (bad) atomicOr(status, 1);
 }
 
@@ -620,9 +682,10 @@ size_t schur_value_bytes(int tier) {
 }
 
 void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b) {
-  // bottom size by register budget; six middle levels (64 bottom states)
+  // bottom size by register budget (the defaults are the fastest measured
+  // at n = 12..30); six middle levels (64 bottom states)
   const int sb_max = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
-  int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 3 : 2);
+  int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
   if (sb_req > 0) sb = sb_req < sb_max ? sb_req : sb_max;
   if (sb > n) sb = n;
   int sm = sb + 6;
@@ -672,19 +735,29 @@ hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const i
   return hipGetLastError();
 }
 
+// Wavefronts per workgroup of the middle + bottom kernel: two where a
+// wavefront's registers fit twice in a SIMD (binary64 and double-double),
+// else one.
+template <class TT>
+constexpr int leaf_waves() {
+  return TT::id == TOR_QD ? 1 : 2;
+}
+
 template <class TT, int SB>
 static hipError_t launch_leaf_t(const void* mat, const void* g, const int32_t* m, int s_m, int nst,
                                 int n, void* partials, int32_t* status, int grid, hipStream_t st) {
   using R = typename TT::R;
   using Acc = typename TT::Acc;
-  hipLaunchKernelGGL((leaf_kernel<TT, SB>), dim3(grid), dim3(64), 0, st, (const R*)mat, (const R*)g,
-                     m, s_m, nst, n, (Acc*)partials, status);
+  constexpr int W = leaf_waves<TT>();
+  const int blocks = grid < (nst + W - 1) / W ? grid : (nst + W - 1) / W;
+  hipLaunchKernelGGL((leaf_kernel<TT, SB, W>), dim3(blocks), dim3(64 * W), 0, st, (const R*)mat,
+                     (const R*)g, m, s_m, nst, n, (Acc*)partials, status);
   return hipGetLastError();
 }
 
 template <class TT, int SB>
 static const void* leaf_fn() {
-  return reinterpret_cast<const void*>(&leaf_kernel<TT, SB>);
+  return reinterpret_cast<const void*>(&leaf_kernel<TT, SB, leaf_waves<TT>()>);
 }
 
 // Compiled (tier, s_b) combinations: s_b is the tier's register budget, or n
@@ -725,7 +798,8 @@ hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* 
 }
 
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu) {
-#define CALL(TT, SBV) hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, leaf_fn<TT, SBV>(), 64, 0)
+#define CALL(TT, SBV) \
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, leaf_fn<TT, SBV>(), 64 * leaf_waves<TT>(), 0)
   TOR_LEAF_DISPATCH(CALL)
 #undef CALL
 }
