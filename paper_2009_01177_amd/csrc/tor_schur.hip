@@ -563,8 +563,47 @@ struct Leaf {
       return;
     }
     const int zz = lane < (1 << L) ? lane >> 1 : 0;
-    const bool inc = (lane & 1) != 0;
+    last_level(cur + zz * odd_up(psize(SB + 1)), cg[zz], cm[zz], L, lane, bad, leaf, lg, lm);
+  }
+
+  // The same, but the lane's pair state (all of it: lane 0 takes the whole
+  // state when L == 0) is only copied into registers P, pg, pm; the last
+  // level is then formed by last_level() outside the expansion.
+  __device__ __forceinline__ static void expand_pair(SMEM& sm, const R* mat, const R* gin,
+                                                     const int32_t* min_, int zn, int nstates, int s_m,
+                                                     int L, int ps0, int lane, bool& bad, R& v0, R& v1,
+                                                     R& v2, R& v3, R& g, int32_t& m, R (&P)[NP], R& pg,
+                                                     int32_t& pm) {
+    store(sm, ps0, lane, v0, v1, v2, v3, g, m);
+    if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, g, m);
+    wave_sync();
+    R* cur;
+    R* cg;
+    int32_t* cm;
+    middle(sm, s_m, L, lane, bad, cur, cg, cm);
+    const int zz = (L == 0 || lane >= (1 << L)) ? 0 : lane >> 1;
     const R* T = cur + zz * odd_up(psize(SB + 1));
+#pragma unroll
+    for (int e = 0; e < NP; ++e) P[e] = T[e];
+    pg = cg[zz];
+    pm = cm[zz];
+  }
+
+  // The lane's bottom state from its pair state T (registers or LDS) of the
+  // last middle level: both children run the same code, the excluded one
+  // with zero pivot multipliers, whose update leaves every entry unchanged.
+  // With L == 0 the state is the bottom state itself.
+  template <class Src>
+  __device__ __forceinline__ static void last_level(const Src& T, const R& tg, int32_t tm, int L, int lane,
+                                                    bool& bad, R (&leaf)[psize(SB)], R& lg, int32_t& lm) {
+    if (L == 0) {
+#pragma unroll
+      for (int e = 0; e < psize(SB); ++e) leaf[e] = T[e];
+      lg = tg;
+      lm = tm;
+      return;
+    }
+    const bool inc = (lane & 1) != 0;
     const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
     if (inc && lane < (1 << L) && !pv.ok) bad = true;
     const R zero = r_zero<R>();
@@ -580,8 +619,8 @@ struct Leaf {
     for (int a = 0; a < 2 * SB; ++a)
 #pragma unroll
       for (int b = 0; b <= a; ++b) leaf[pk(a, b)] = r_fms2(T[pk(a + 2, b + 2)], u0[a], u0[b], u1[a], u1[b]);
-    lg = inc ? r_mul(r_mul(cg[zz], pv.rl0), pv.rl1) : cg[zz];
-    lm = cm[zz] + (inc ? 1 : 0);
+    lg = inc ? r_mul(r_mul(tg, pv.rl0), pv.rl1) : tg;
+    lm = tm + (inc ? 1 : 0);
   }
 
   // The bottom of the lane's state and the wave's fixed-order totals,
@@ -616,6 +655,16 @@ constexpr int leaf_waves_per_simd() {
   return (W == 2 && !(TT::id == TOR_DD && SB >= 4)) ? 2 : 1;
 }
 
+// Whether the expanding wavefront hands its lanes' pair states over in
+// registers, so that the last middle level runs beside the bottom instead
+// of inside the expansion (which the other wavefront waits for): where the
+// registers allow it without lowering the occupancy (double-double with a
+// four-mode bottom runs one wavefront per SIMD either way).
+template <class TT, int SB, int W>
+constexpr bool leaf_pair_in_registers() {
+  return W == 2 && TT::id == TOR_DD && SB >= 4;
+}
+
 template <class TT, int SB, int W>
 __global__ __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf_kernel(const typename TT::R* __restrict__ mat,
@@ -642,9 +691,11 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
   const int ps0 = psize(s_m);
   const int zstride = W * (int)gridDim.x;
   bool bad = false;
-  R v0 = r_zero<R>(), v1 = v0, v2 = v0, v3 = v0, g = v0, lg = v0;
-  int32_t m = 0, lm = 0;
+  constexpr bool PR = leaf_pair_in_registers<TT, SB, W>();
+  R v0 = r_zero<R>(), v1 = v0, v2 = v0, v3 = v0, g = v0, lg = v0, pg = v0;
+  int32_t m = 0, lm = 0, pm = 0;
   R leaf[psize(SB)];
+  R P[LF::NP];
 
   const int zb = W * (int)blockIdx.x;
   if (zb + wv < nstates) LF::fetch(mat, gin, min_, zb + wv, ps0, lane, v0, v1, v2, v3, g, m);
@@ -657,11 +708,19 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
   if (W == 2 && wv == 1) __syncthreads();
   for (int t = 0; t < rounds; ++t) {
     const int z = zb + wv + t * zstride;
-    if (z < nstates)
-      LF::expand(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, g, m,
-                 leaf, lg, lm);
+    if (z < nstates) {
+      if constexpr (PR)
+        LF::expand_pair(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, g,
+                        m, P, pg, pm);
+      else
+        LF::expand(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, g, m,
+                   leaf, lg, lm);
+    }
     if (W == 2) __syncthreads(); else wave_sync();
-    if (z < nstates) LF::finish(leaf, lg, lm, L, lane, n, z, partials, bad);
+    if (z < nstates) {
+      if constexpr (PR) LF::last_level(P, pg, pm, L, lane, bad, leaf, lg, lm);
+      LF::finish(leaf, lg, lm, L, lane, n, z, partials, bad);
+    }
     if (W == 2) __syncthreads();
   }
   if (W == 2 && wv == 0) __syncthreads();
