@@ -69,8 +69,9 @@ def schur_node_flops(sp: int, tier: str) -> int:
 
 
 def acc_flops(tier: str) -> int:
-    """Compensated accumulation of one term into the signed and magnitude sums."""
-    return 2 * 10 if tier == "fp64" else 2 * 20
+    """Accumulation of one term into a lane's signed and magnitude sums
+    (two_sum of the leading parts, low parts added in binary64)."""
+    return 2 * 7 if tier == "fp64" else 2 * 8
 
 
 def schur_flops(n: int, tier: str, dmin: int = 0) -> int:

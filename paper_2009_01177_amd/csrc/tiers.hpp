@@ -217,6 +217,12 @@ __device__ __forceinline__ R wave_sum(R v) {
 // Tier descriptors
 // --------------------------------------------------------------------------
 
+// acc_add: accumulate one term, normalised.  acc_run / acc_fix: the same
+// for a run of k terms summed by one lane: the leading parts through
+// two_sum, every low-order part (the terms' and the two_sum errors) added
+// into the low word in binary64, and one renormalisation at the end.  The
+// extra error is within k^2 u^2 of the sum of the magnitudes involved
+// (k <= 32 in the Schur bottom).
 struct TierF64 {
   using R = double;
   using Acc = dd;
@@ -224,6 +230,16 @@ struct TierF64 {
   __device__ static Acc acc_zero() { return dd{0.0, 0.0}; }
   __device__ static Acc acc_add(Acc a, R t) { return prec::dd_add_d(a, t); }
   __device__ static Acc acc_merge(Acc a, Acc b) { return prec::dd_add(a, b); }
+  __device__ static Acc acc_run(Acc a, R t) {
+    double s, e;
+    prec::two_sum(a.hi, t, s, e);
+    return dd{s, a.lo + e};
+  }
+  __device__ static Acc acc_fix(Acc a) {
+    dd z;
+    prec::two_sum(a.hi, a.lo, z.hi, z.lo);
+    return z;
+  }
 };
 
 struct TierDD {
@@ -233,6 +249,16 @@ struct TierDD {
   __device__ static Acc acc_zero() { return dd{0.0, 0.0}; }
   __device__ static Acc acc_add(Acc a, R t) { return prec::dd_add(a, t); }
   __device__ static Acc acc_merge(Acc a, Acc b) { return prec::dd_add(a, b); }
+  __device__ static Acc acc_run(Acc a, R t) {
+    double s, e;
+    prec::two_sum(a.hi, t.hi, s, e);
+    return dd{s, a.lo + (t.lo + e)};
+  }
+  __device__ static Acc acc_fix(Acc a) {
+    dd z;
+    prec::two_sum(a.hi, a.lo, z.hi, z.lo);
+    return z;
+  }
 };
 
 struct TierQD {
@@ -242,6 +268,8 @@ struct TierQD {
   __device__ static Acc acc_zero() { return qd{{0.0, 0.0, 0.0, 0.0}}; }
   __device__ static Acc acc_add(Acc a, R t) { return prec::qd_add(a, t); }
   __device__ static Acc acc_merge(Acc a, Acc b) { return prec::qd_add(a, b); }
+  __device__ static Acc acc_run(Acc a, R t) { return prec::qd_add(a, t); }
+  __device__ static Acc acc_fix(Acc a) { return a; }
 };
 
 // |x| of a value whose sign is carried by its leading component

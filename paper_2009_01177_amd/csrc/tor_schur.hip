@@ -75,7 +75,8 @@ __device__ __forceinline__ qd r_from_sum<qd>(double a, double b, double c) {
   return prec::qd_add_d(qd{{s, e, 0.0, 0.0}}, c);
 }
 
-// Accumulators of one lane: signed sum and sum of magnitudes.
+// Accumulators of one lane: signed sum and sum of magnitudes (a run of
+// terms, renormalised once by acc_fix).
 template <class TT>
 struct LaneAcc {
   typename TT::Acc t, a;
@@ -84,8 +85,8 @@ struct LaneAcc {
 // Emit the term of a completed subset: (-1)^(n-m) g.
 template <class TT>
 __device__ __forceinline__ void emit_term(LaneAcc<TT>& acc, const typename TT::R& g, int m, int n) {
-  acc.t = TT::acc_add(acc.t, ((n - m) & 1) ? r_neg(g) : g);
-  acc.a = TT::acc_add(acc.a, g);
+  acc.t = TT::acc_run(acc.t, ((n - m) & 1) ? r_neg(g) : g);
+  acc.a = TT::acc_run(acc.a, g);
 }
 
 // Pivot of the 2x2 block at rows (2i, 2i+1): reciprocal square roots of the
@@ -631,8 +632,8 @@ struct Leaf {
     acc.t = TT::acc_zero();
     acc.a = TT::acc_zero();
     if (lane < (1 << L)) Bottom<TT, SB>::run(leaf, lg, lm, n, acc, bad);
-    const Acc tt = wave_total<TT>(acc.t);
-    const Acc ta = wave_total<TT>(acc.a);
+    const Acc tt = wave_total<TT>(TT::acc_fix(acc.t));
+    const Acc ta = wave_total<TT>(TT::acc_fix(acc.a));
     if (lane == 0) {
       partials[(size_t)z * 2] = tt;
       partials[(size_t)z * 2 + 1] = ta;
