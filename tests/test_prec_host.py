@@ -1,0 +1,103 @@
+"""The extended-precision arithmetic of the HIP path (csrc/prec.hpp, which is
+host-compatible), compiled for the host and checked against exact rational
+arithmetic: the fused Schur updates t - ab and t - ab - cd within their
+stated bounds, results normalised, and the composed double-double
+operations within their published ones.  CPU only."""
+import os
+import subprocess
+from fractions import Fraction as F
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+U = F(1, 2 ** 53)
+
+HARNESS = r"""
+#include "prec.hpp"
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+using namespace prec;
+int main(int argc, char** argv) {
+  std::mt19937_64 g(atoi(argv[1]));
+  const int count = atoi(argv[2]);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  std::uniform_int_distribution<int> E(-30, 30);
+  auto mk = [&](double scale) {
+    const double h = ldexp(U(g), E(g) / 10) * scale;
+    const double l = U(g) * 0x1p-54 * h;
+    dd z;
+    fast_two_sum(h, l, z.hi, z.lo);
+    return z;
+  };
+  for (int i = 0; i < count; ++i) {
+    const int mode = i % 4;
+    dd a = mk(1), b = mk(1), c = mk(1), d = mk(1), t = mk(1);
+    if (mode == 1) t = dd_add(dd_mul(a, b), dd_mul(c, d));   // near-total cancellation
+    if (mode == 2) t = dd_mul(a, b);                          // t - ab ~ 0
+    if (mode == 3) { c = a; d = b; }                          // repeated product
+    const dd z1 = dd_fms(t, a, b), z2 = dd_fms2(t, a, b, c, d);
+    const dd m = dd_mul(a, b), s = dd_add(t, c);
+    printf("%a %a %a %a %a %a %a %a %a %a %a %a %a %a %a %a %a %a\n", t.hi, t.lo, a.hi, a.lo, b.hi, b.lo,
+           c.hi, c.lo, d.hi, d.lo, z1.hi, z1.lo, z2.hi, z2.lo, m.hi, m.lo, s.hi, s.lo);
+  }
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def cases(tmp_path_factory):
+    d = tmp_path_factory.mktemp("prec")
+    src, exe = d / "h.cpp", d / "h"
+    src.write_text(HARNESS)
+    r = subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-I",
+                        os.path.join(ROOT, "paper_2009_01177_amd", "csrc"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe), "7", "6000"], capture_output=True, text=True, check=True).stdout
+    rows = []
+    for line in out.splitlines():
+        v = [F(float.fromhex(x)) for x in line.split()]
+        rows.append([(v[2 * k], v[2 * k + 1]) for k in range(9)])
+    return rows
+
+
+def _val(p):
+    return p[0] + p[1]
+
+
+def _normalised(p):
+    hi, lo = p
+    return hi == 0 and lo == 0 or abs(lo) <= U * abs(hi)
+
+
+def test_fused_update_t_minus_ab(cases):
+    worst = F(0)
+    for t, a, b, c, d, z1, z2, m, s in cases:
+        mag = abs(_val(t)) + abs(_val(a) * _val(b))
+        err = abs(_val(z1) - (_val(t) - _val(a) * _val(b)))
+        assert err <= 12 * U * U * mag
+        assert _normalised(z1)
+        worst = max(worst, err / (U * U * mag) if mag else F(0))
+    assert worst > 0  # the cases do exercise rounding
+
+
+def test_fused_update_t_minus_ab_minus_cd(cases):
+    for t, a, b, c, d, z1, z2, m, s in cases:
+        ab, cd = _val(a) * _val(b), _val(c) * _val(d)
+        mag = abs(_val(t)) + abs(ab) + abs(cd)
+        err = abs(_val(z2) - (_val(t) - ab - cd))
+        assert err <= 22 * U * U * mag
+        assert _normalised(z2)
+
+
+def test_composed_operations_meet_their_published_bounds(cases):
+    # DWTimesDW (FMA form) 4u^2, AccurateDWPlusDW 3u^2 + 13u^3, relative
+    for t, a, b, c, d, z1, z2, m, s in cases:
+        ab = _val(a) * _val(b)
+        if ab != 0:
+            assert abs(_val(m) - ab) <= 4 * U * U * abs(ab)
+        tc = _val(t) + _val(c)
+        if tc != 0:
+            assert abs(_val(s) - tc) <= (3 * U * U + 13 * U ** 3) * abs(tc)
