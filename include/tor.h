@@ -247,8 +247,10 @@ typedef struct tor_selector {
   double mean[TOR_NFEAT], std[TOR_NFEAT]; /* input standardisation */
   double fmin[TOR_NFEAT], fmax[TOR_NFEAT]; /* training range; outside it the
                                               bound estimate decides */
-  double log10_c[3]; /* per tier: log10 C_t in |dTor|/|Tor| <= C_t kappa u_t,
-                        calibrated on training data */
+  double log10_c[3]; /* per tier t: the error model
+                        log10(|dTor|/|Tor|) <= log10_c[t] + slope[t] (log10 kappa
+                        + margin) + log10 u_t, both calibrated on training data */
+  double slope[3];   /* per tier, in (0, 2]; 1: error proportional to kappa */
   double margin;     /* extra log10 safety margin on the prediction */
   int32_t nmin, nmax; /* training range of n */
   int32_t trained;    /* 0: no network, the bound estimate decides */

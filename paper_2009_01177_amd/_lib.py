@@ -63,6 +63,7 @@ class TorSelectorC(ctypes.Structure):
         ("fmin", ctypes.c_double * 12),
         ("fmax", ctypes.c_double * 12),
         ("log10_c", ctypes.c_double * 3),
+        ("slope", ctypes.c_double * 3),
         ("margin", ctypes.c_double),
         ("nmin", ctypes.c_int32),
         ("nmax", ctypes.c_int32),
@@ -94,6 +95,20 @@ def _strerror(code: int) -> str:
         return "error %d" % code
 
 
+def _torch_gpu_first():
+    """Initialise PyTorch's GPU runtime before the library's.  The library is
+    linked against the system HIP runtime and PyTorch carries its own; when
+    the library's initialises the device first, PyTorch then finds no GPU in
+    that process.  Counting devices does not initialise anything, so a host
+    without a GPU is left alone."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover - torch is a dependency
+        return
+    if torch.cuda.device_count() > 0:
+        torch.cuda.init()
+
+
 def lib():
     """The loaded library; raises if it has not been built."""
     global _lib
@@ -103,6 +118,7 @@ def lib():
         raise ImportError(
             "libtor_hip.so is not built (run `python -m paper_2009_01177_amd.build` "
             "or __graft_entry__.build())")
+    _torch_gpu_first()
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     dp = ctypes.POINTER(ctypes.c_double)

@@ -736,7 +736,7 @@ int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, con
       } else {
         t = TOR_QD;
         for (int c = TOR_FP64; c <= TOR_DD; ++c) {
-          if (sel.log10_c[c] + hp[i] + sel.margin + tier_unit_log10(c) <= ltau) {
+          if (sel.log10_c[c] + sel.slope[c] * (hp[i] + sel.margin) + tier_unit_log10(c) <= ltau) {
             t = c;
             break;
           }
@@ -787,7 +787,7 @@ int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const
     for (int k = 0; k < batch; ++k) {
       if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t) {
         cls.push_back(k);
-        const double lerr = sel.log10_c[t] + pred[k] + sel.margin + tier_unit_log10(t);
+        const double lerr = sel.log10_c[t] + sel.slope[t] * (pred[k] + sel.margin) + tier_unit_log10(t);
         if (src[k] == 0 && lerr >= ltau - window) near.push_back(k);
       }
     }
@@ -1095,6 +1095,8 @@ int tor_selector_set(const tor_selector_t* sel) {
       for (int i = 0; i < TOR_NFEAT; ++i)
         if (!(sel->std[i] > 0.0)) return TOR_EINVAL;
       if (sel->nmin < 1 || sel->nmax < sel->nmin || sel->nmax > TOR_NMAX) return TOR_EINVAL;
+      for (int t = 0; t < 3; ++t)
+        if (!(sel->slope[t] > 0.0 && sel->slope[t] <= 2.0)) return TOR_EINVAL;
     }
     g_sel = *sel;
   } else {
@@ -1122,13 +1124,14 @@ int tor_selector_save(const char* path) {
     for (int i = 0; i < cnt; ++i) fprintf(f, " %.17g", v[i]);
     fprintf(f, "\n");
   };
-  fprintf(f, "tor_selector 1\n");
+  fprintf(f, "tor_selector 2\n");
   arr("theta", sel.theta, TOR_MLP_PARAMS);
   arr("mean", sel.mean, TOR_NFEAT);
   arr("std", sel.std, TOR_NFEAT);
   arr("fmin", sel.fmin, TOR_NFEAT);
   arr("fmax", sel.fmax, TOR_NFEAT);
   arr("log10_c", sel.log10_c, 3);
+  arr("slope", sel.slope, 3);
   arr("margin", &sel.margin, 1);
   fprintf(f, "nrange %d %d\ntrained %d\n", sel.nmin, sel.nmax, sel.trained);
   const int ok = fclose(f) == 0;
@@ -1143,7 +1146,10 @@ int tor_selector_load(const char* path) {
   memset(&sel, 0, sizeof(sel));
   char name[64];
   int version = 0, rc = TOR_OK;
-  if (fscanf(f, "%63s %d", name, &version) != 2 || strcmp(name, "tor_selector") != 0 || version != 1)
+  // version 1 files predate the slope: their error model is proportional
+  // to kappa (slope 1)
+  if (fscanf(f, "%63s %d", name, &version) != 2 || strcmp(name, "tor_selector") != 0 ||
+      (version != 1 && version != 2))
     rc = TOR_EINVAL;
   auto arr = [&](const char* want, double* v, int cnt) {
     int c = 0;
@@ -1161,6 +1167,11 @@ int tor_selector_load(const char* path) {
   arr("fmin", sel.fmin, TOR_NFEAT);
   arr("fmax", sel.fmax, TOR_NFEAT);
   arr("log10_c", sel.log10_c, 3);
+  if (version >= 2) {
+    arr("slope", sel.slope, 3);
+  } else {
+    for (int t = 0; t < 3; ++t) sel.slope[t] = 1.0;
+  }
   arr("margin", &sel.margin, 1);
   if (rc == TOR_OK && fscanf(f, "%63s %d %d", name, &sel.nmin, &sel.nmax) != 3) rc = TOR_EINVAL;
   if (rc == TOR_OK && fscanf(f, "%63s %d", name, &sel.trained) != 2) rc = TOR_EINVAL;

@@ -3,8 +3,8 @@
 The selector predicts y = log10(S_abs / |Tor|), the cancellation ratio that
 decides how many of a tier's bits survive the alternating sum (Sec. 5.1),
 from the 12 features of tor_features.  Labels come from the library's own
-quad-double evaluations; the per-tier error factors C_t of
-|dTor|/|Tor| <= C_t kappa u_t are calibrated from FP64 and double-double
+quad-double evaluations; the per-tier error model
+|dTor|/|Tor| <= C_t kappa^s_t u_t is calibrated from FP64 and double-double
 evaluations of the same instances.  Forward passes, gradients and Adam steps
 run in the library's HIP kernels (tor_mlp_forward / tor_mlp_grad /
 tor_mlp_adam); this module only drives them.
@@ -136,22 +136,37 @@ def predict(theta, mean, std, X) -> np.ndarray:
                            torch.from_numpy(np.ascontiguousarray(X)).to(dev)).cpu().numpy()
 
 
-def calibrate(lab: Labels, slack: float = 0.3) -> list:
-    """log10 C_t: the worst observed err_t / (kappa u_t) per tier, plus slack."""
-    out = []
+def calibrate(lab: Labels, slack: float = 0.3):
+    """The per-tier error model log10(err_t / u_t) <= c_t + s_t log10 kappa:
+    for each slope s_t in [0.3, 1] the intercept is the upper envelope of the
+    training points; the slope kept is the one whose envelope lies lowest on
+    average over them (rounding errors of the alternating sum grow more
+    slowly than kappa); the intercept gets `slack` decades on top.
+    Returns (log10_c, slopes), three entries each (QD shares DD's)."""
+    cs, ss = [], []
     for t in (0, 1):
         e = lab.err[t]
         ok = e > 0
         if not ok.any():
-            out.append(0.0)
+            cs.append(0.0)
+            ss.append(1.0)
             continue
-        r = np.log10(e[ok]) - lab.y[ok] - math.log10(U[t])
-        out.append(float(np.max(r)) + slack)
-    out.append(out[-1])
-    return out
+        y = lab.y[ok]
+        r = np.log10(e[ok]) - math.log10(U[t])
+        best = None
+        for s in np.arange(0.30, 1.0001, 0.01):
+            c = float(np.max(r - s * y))
+            height = float(np.mean(c + s * y))
+            if best is None or height < best[0]:
+                best = (height, c, float(s))
+        cs.append(best[1] + slack)
+        ss.append(best[2])
+    cs.append(cs[-1])
+    ss.append(ss[-1])
+    return cs, ss
 
 
-def make_selector(theta, mean, std, lab: Labels, log10_c, margin: float = 0.5):
+def make_selector(theta, mean, std, lab: Labels, log10_c, slopes=(1.0, 1.0, 1.0), margin: float = 0.5):
     sel = _lib.TorSelectorC()
     for i, v in enumerate(theta):
         sel.theta[i] = float(v)
@@ -162,6 +177,7 @@ def make_selector(theta, mean, std, lab: Labels, log10_c, margin: float = 0.5):
         sel.fmax[i] = float(lab.X[:, i].max())
     for t in range(3):
         sel.log10_c[t] = float(log10_c[t])
+        sel.slope[t] = float(slopes[t])
     sel.margin = float(margin)
     sel.nmin = int(lab.n.min())
     sel.nmax = int(lab.n.max())
@@ -176,8 +192,8 @@ def fit_and_install(count: int = 3000, nlo: int = 6, nhi: int = 24, seed: int = 
     lab = label(Os)
     theta, mean, std, losses = train(lab.X, lab.y, epochs=epochs, seed=seed,
                                      log_every=50 if verbose else 0)
-    log10_c = calibrate(lab)
-    sel = make_selector(theta, mean, std, lab, log10_c)
+    log10_c, slopes = calibrate(lab)
+    sel = make_selector(theta, mean, std, lab, log10_c, slopes)
     tor_selector_set(sel)
     if path:
         from .api import tor_selector_save
@@ -221,12 +237,12 @@ if __name__ == "__main__":
     print(f"[selector] labelled in {time.time() - t0:.1f} s; log10 kappa "
           f"{lab.y.min():.2f}..{lab.y.max():.2f}", flush=True)
     theta, mean, std, losses = train(lab.X, lab.y, epochs=a.epochs, seed=a.seed, log_every=50)
-    log10_c = calibrate(lab)
+    log10_c, slopes = calibrate(lab)
     pred = predict(theta, mean, std, lab.X)
     under = float(np.mean(pred < lab.y))
-    print(f"[selector] loss {losses[0]:.3f} -> {losses[-1]:.4f}; log10 C = {log10_c}; "
+    print(f"[selector] loss {losses[0]:.3f} -> {losses[-1]:.4f}; log10 C = {log10_c}; slopes = {slopes}; "
           f"fraction under-predicted {under:.3f}", flush=True)
-    sel = make_selector(theta, mean, std, lab, log10_c)
+    sel = make_selector(theta, mean, std, lab, log10_c, slopes)
     tor_selector_set(sel)
     from .api import tor_selector_save
     tor_selector_save(a.out)

@@ -8,6 +8,7 @@ error of any tier scales with S_abs = sum |terms|, not with |Tor|):
     tol = 1e-12 (FP64), 1e-25 (DD), 1e-30 (QD: the oracle's own binary128
     limit; QD's 1e-50 is checked against 80-digit brute force instead).
 """
+import os
 from fractions import Fraction
 
 import mpmath
@@ -20,6 +21,7 @@ import oracle
 pytestmark = pytest.mark.gpu
 
 TOL = {"fp64": 1e-12, "dd": 1e-25, "qd": 1e-30}
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module")
@@ -285,3 +287,21 @@ def test_leading_dimension(tor):
     a = tor.tor_eval(t, tier="dd")
     b = tor.tor_eval(O, tier="dd")
     assert a.expansion == b.expansion
+
+
+def test_library_before_torch_keeps_torch_on_the_gpu(tor):
+    """Regression: initialising the library before PyTorch has touched the
+    GPU used to leave PyTorch without a device in that process.  Runs in a
+    fresh interpreter, library first."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_2009_01177_amd as t\n"
+            "t.tor_init()\n"
+            "import numpy as np, torch, gbs_inputs as g\n"
+            "O = g.random_instance(6, 5)\n"
+            "r = t.tor_eval(torch.from_numpy(O).cuda(), tier='fp64')\n"
+            "print('ok', r.status, torch.cuda.device_count())\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert out.stdout.split()[:2] == ["ok", "0"], out.stdout

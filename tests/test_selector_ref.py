@@ -121,6 +121,7 @@ def test_selector_file_round_trip(tmp_path):
         sel.mean[i], sel.std[i] = rng.normal(), 1.0 + rng.random()
         sel.fmin[i], sel.fmax[i] = -1.0 - i, 1.0 + i
     sel.log10_c[0], sel.log10_c[1], sel.log10_c[2] = 1.5, 2.0, 2.5
+    sel.slope[0], sel.slope[1], sel.slope[2] = 0.55, 0.8, 1.0
     sel.margin = 0.7
     sel.nmin, sel.nmax, sel.trained = 6, 24, 1
     old = tor.tor_selector_get()
@@ -134,6 +135,37 @@ def test_selector_file_round_trip(tmp_path):
         back = tor.tor_selector_get()
         assert list(back.theta) == list(sel.theta)
         assert list(back.std) == list(sel.std) and back.margin == sel.margin
+        assert list(back.slope) == list(sel.slope) and list(back.log10_c) == list(sel.log10_c)
         assert (back.nmin, back.nmax, back.trained) == (6, 24, 1)
+    finally:
+        tor.tor_selector_set(old)
+
+
+def test_selector_file_version_1_reads_as_slope_one(tmp_path):
+    """Files written before the error model had a slope load with slope 1."""
+    import paper_2009_01177_amd as tor
+    from paper_2009_01177_amd import _lib
+    old = tor.tor_selector_get()
+    try:
+        sel = _lib.TorSelectorC()
+        for i in range(12):
+            sel.std[i], sel.fmax[i] = 1.0, 1.0
+        for t in range(3):
+            sel.slope[t] = 0.5
+        sel.nmin, sel.nmax, sel.trained = 6, 24, 1
+        tor.tor_selector_set(sel)
+        p = os.path.join(tmp_path, "v2.txt")
+        tor.tor_selector_save(p)
+        lines = open(p).read().splitlines()
+        assert lines[0] == "tor_selector 2"
+        v1 = ["tor_selector 1"] + [ln for ln in lines[1:] if not ln.startswith("slope ")]
+        p1 = os.path.join(tmp_path, "v1.txt")
+        open(p1, "w").write("\n".join(v1) + "\n")
+        tor.tor_selector_load(p1)
+        assert list(tor.tor_selector_get().slope) == [1.0, 1.0, 1.0]
+        # a slope outside (0, 2] is refused
+        sel.slope[0] = 0.0
+        with pytest.raises(tor.TorError):
+            tor.tor_selector_set(sel)
     finally:
         tor.tor_selector_set(old)
