@@ -493,26 +493,63 @@ struct Leaf {
         // children's g and |Z|
         const int nmo = S - 1;
         const DivBy dm(nmo);
-        for (int idx = lane; idx < ns * nmo; idx += 64) {
-          const int zz = dm.q(idx), i = idx - zz * nmo;
-          const R* T = cur + zz * ps;
-          const int r = 2 * i + 2;
-          const R a0 = T[pk(r, 0)], a1 = T[pk(r, 1)];
-          const R b0 = T[pk(r + 1, 0)], b1 = T[pk(r + 1, 1)];
-          R rd;
-          const Pivot<R> pv = make_pivot_det(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)], rd);
-          if (!pv.ok) bad = true;
-          const R u0a = r_mul(a0, pv.rl0), u0b = r_mul(b0, pv.rl0);
-          R* U = sm.u + zz * urs + 4 * i;
-          U[0] = u0a;
-          U[1] = r_mul(r_fms(a1, u0a, pv.l10), pv.rl1);
-          U[2] = u0b;
-          U[3] = r_mul(r_fms(b1, u0b, pv.l10), pv.rl1);
-          if (i == 0) {
-            ng[2 * zz] = cg[zz];
-            nm[2 * zz] = cm[zz];
-            ng[2 * zz + 1] = r_mul(cg[zz], rd);
-            nm[2 * zz + 1] = cm[zz] + 1;
+        if (ns * nmo > 64) {
+          // more than one pass's worth: two items per lane per pass, their
+          // pivot chains side by side (an item past the end repeats the last
+          // one and is not stored)
+          const int totu = ns * nmo;
+          for (int i0 = lane; i0 < totu; i0 += 128) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+              const int idx = min(i0 + 64 * k, totu - 1);
+              const int zz = dm.q(idx), i = idx - zz * nmo;
+              const R* T = cur + zz * ps;
+              const int r = 2 * i + 2;
+              const R a0 = T[pk(r, 0)], a1 = T[pk(r, 1)];
+              const R b0 = T[pk(r + 1, 0)], b1 = T[pk(r + 1, 1)];
+              R rd;
+              const Pivot<R> pv = make_pivot_det(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)], rd);
+              if (!pv.ok) bad = true;
+              const R u0a = r_mul(a0, pv.rl0), u0b = r_mul(b0, pv.rl0);
+              const R u1a = r_mul(r_fms(a1, u0a, pv.l10), pv.rl1);
+              const R u1b = r_mul(r_fms(b1, u0b, pv.l10), pv.rl1);
+              if (i0 + 64 * k < totu) {
+                R* U = sm.u + zz * urs + 4 * i;
+                U[0] = u0a;
+                U[1] = u1a;
+                U[2] = u0b;
+                U[3] = u1b;
+                if (i == 0) {
+                  ng[2 * zz] = cg[zz];
+                  nm[2 * zz] = cm[zz];
+                  ng[2 * zz + 1] = r_mul(cg[zz], rd);
+                  nm[2 * zz + 1] = cm[zz] + 1;
+                }
+              }
+            }
+          }
+        } else {
+          for (int idx = lane; idx < ns * nmo; idx += 64) {
+            const int zz = dm.q(idx), i = idx - zz * nmo;
+            const R* T = cur + zz * ps;
+            const int r = 2 * i + 2;
+            const R a0 = T[pk(r, 0)], a1 = T[pk(r, 1)];
+            const R b0 = T[pk(r + 1, 0)], b1 = T[pk(r + 1, 1)];
+            R rd;
+            const Pivot<R> pv = make_pivot_det(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)], rd);
+            if (!pv.ok) bad = true;
+            const R u0a = r_mul(a0, pv.rl0), u0b = r_mul(b0, pv.rl0);
+            R* U = sm.u + zz * urs + 4 * i;
+            U[0] = u0a;
+            U[1] = r_mul(r_fms(a1, u0a, pv.l10), pv.rl1);
+            U[2] = u0b;
+            U[3] = r_mul(r_fms(b1, u0b, pv.l10), pv.rl1);
+            if (i == 0) {
+              ng[2 * zz] = cg[zz];
+              nm[2 * zz] = cm[zz];
+              ng[2 * zz + 1] = r_mul(cg[zz], rd);
+              nm[2 * zz + 1] = cm[zz] + 1;
+            }
           }
         }
       }
