@@ -42,9 +42,10 @@ if ROOT not in sys.path:
 PEAK_FP64_TFLOPS = 78.6  # MI355X FP64 vector: 256 CU x 2.4 GHz x 128 flop/clk/CU
 # FP64 operations per complex multiply-add in each tier's arithmetic:
 #   FP64: 4 fused multiply-adds = 8 flops;
-#   DD  : 4 fused double-double multiply-adds t - ab (21 flops each:
-#         exact leading product, fma cross terms, two error-free sums) = 84.
-FLOPS_PER_CFMA = {"fp64": 8, "dd": 84}
+#   DD  : 4 fused double-double multiply-adds t - ab (18 flops each:
+#         exact leading product, fma cross terms, an error-free sum and a
+#         renormalisation) = 72.
+FLOPS_PER_CFMA = {"fp64": 8, "dd": 72}
 
 
 def kernel_flops(n, tier, algo, dmid):
@@ -62,10 +63,11 @@ def schur_node_flops(sp: int, tier: str) -> int:
         # entry: 2 FMA; row: mul, FMA, mul; pivot: 2 rsqrt (estimate and a
         # Newton step, 7), mul, FMA, 2 mul for g
         return 4 * ent + 4 * rows + 19
-    # DD: entry t - ab - cd fused (36); row: 2 DWTimesDW (12 each) and one
-    # fused t - ab (21); pivot: 2 DD rsqrt (29 each), a DWTimesDW, a fused
-    # t - ab, 2 DWTimesDW for g
-    return 36 * ent + 45 * rows + 115
+    # DD: entry t - ab - cd fused (33); row: 2 DWTimesDW (12 each) and one
+    # fused t - ab (18); pivot: 2 DD rsqrt (22 each: estimate, binary64 and
+    # double-double Newton steps), a DWTimesDW, a fused t - ab, 2 DWTimesDW
+    # for g
+    return 33 * ent + 42 * rows + 98
 
 
 def acc_flops(tier: str) -> int:

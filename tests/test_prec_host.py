@@ -1,8 +1,9 @@
 """The extended-precision arithmetic of the HIP path (csrc/prec.hpp, which is
 host-compatible), compiled for the host and checked against exact rational
 arithmetic: the fused Schur updates t - ab and t - ab - cd within their
-stated bounds, results normalised, and the composed double-double
-operations within their published ones.  CPU only."""
+stated bounds (15 u^2 and 26 u^2 of the magnitudes), results normalised,
+and the composed double-double operations within their published ones.
+CPU only."""
 import os
 import subprocess
 from fractions import Fraction as F
@@ -77,7 +78,7 @@ def test_fused_update_t_minus_ab(cases):
     for t, a, b, c, d, z1, z2, m, s in cases:
         mag = abs(_val(t)) + abs(_val(a) * _val(b))
         err = abs(_val(z1) - (_val(t) - _val(a) * _val(b)))
-        assert err <= 12 * U * U * mag
+        assert err <= 15 * U * U * mag
         assert _normalised(z1)
         worst = max(worst, err / (U * U * mag) if mag else F(0))
     assert worst > 0  # the cases do exercise rounding
@@ -88,7 +89,7 @@ def test_fused_update_t_minus_ab_minus_cd(cases):
         ab, cd = _val(a) * _val(b), _val(c) * _val(d)
         mag = abs(_val(t)) + abs(ab) + abs(cd)
         err = abs(_val(z2) - (_val(t) - ab - cd))
-        assert err <= 22 * U * U * mag
+        assert err <= 26 * U * U * mag
         assert _normalised(z2)
 
 
