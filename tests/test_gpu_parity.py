@@ -305,3 +305,21 @@ def test_library_before_torch_keeps_torch_on_the_gpu(tor):
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr[-2000:]
     assert out.stdout.split()[:2] == ["ok", "0"], out.stdout
+
+
+# every compiled bottom size, at n just above its middle depth (two and eight
+# middle states), one to three workgroups: the two-wavefront alternation with
+# short and uneven rounds
+@pytest.mark.parametrize("tier,sb", [("fp64", s) for s in range(1, 6)] + [("dd", s) for s in range(1, 5)]
+                         + [("qd", s) for s in range(1, 3)])
+@pytest.mark.parametrize("extra", [1, 3])
+def test_every_bottom_size_and_small_grids(tor, tier, sb, extra):
+    n = sb + 6 + extra
+    O = g.random_instance(n, 700 + 10 * sb + extra)
+    print(f"[parity] bottom size {sb} tier {tier} n={n}", flush=True)
+    ref = oracle.tor(O)
+    runs = [tor.tor_eval(O, tier=tier, algo="schur", bottom_modes=sb, grid=gr) for gr in (1, 3, 0)]
+    for r in runs:
+        assert r.status == 0
+        assert err_rel(r, ref) <= TOL[tier]
+    assert runs[0].expansion == runs[1].expansion == runs[2].expansion
