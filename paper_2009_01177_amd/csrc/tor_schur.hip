@@ -21,22 +21,24 @@
 // amortised terms, about twelve rank-2 updates of the small trailing
 // matrices, in place of the paper's per-subset elimination (Alg. 1, Sec.
 // 4.2) or even the bordered update of the factor.  g of a child is g times
-// the reciprocal square roots of the two pivots.
+// det(P)^(-1/2).
 //
 // Three levels, one per memory:
 //   top    (HBM)  breadth-first expansion, one launch per decided mode, of
 //                 every state down to depth n - s_m; each state stores its
 //                 packed s_m-mode matrix, g and |Z|.
 //   middle (LDS)  one wavefront per depth-(n - s_m) state expands the next
-//                 s_m - s_b <= 6 modes breadth-first, the entry updates of a
-//                 whole level spread over the lanes; the last of these
-//                 expansions gives each lane one state at depth n - s_b.
+//                 s_m - s_b <= 6 modes breadth-first, the updates of a whole
+//                 level spread over the lanes as 2x2 mode blocks; the last of
+//                 these expansions gives each lane one state at depth n - s_b.
 //   bottom (VGPR) each lane finishes its own state: all 2^s_b subsets of the
 //                 last s_b modes, fully unrolled at compile time with the
 //                 matrices in registers.
-// Every wavefront writes one partial (signed sum, sum of magnitudes) per
-// middle state; the reductions run in a fixed order, so results do not
-// depend on scheduling.
+// Two wavefronts share a workgroup's LDS and take turns: while one expands a
+// state's middle levels, the other runs the register-only bottom of the
+// state it expanded before.  Every wavefront writes one partial (signed sum,
+// sum of magnitudes) per middle state; the reductions run in a fixed order,
+// so results do not depend on scheduling or on the grid.
 #include <hip/hip_runtime.h>
 
 #include "tiers.hpp"
