@@ -97,12 +97,25 @@ def paper_eq9_flops(n: int) -> float:
     return sum(math.comb(n, i) * (32.0 / 3 * i ** 3 + 4 * i * i - 8.0 / 3 * i) for i in range(1, n + 1))
 
 
+def kernel_code_hash() -> str:
+    """sha256 prefix of the Schur kernels' code (tor_schur.hip with its //
+    comments, trailing blanks and empty lines removed, so that a comment edit
+    does not invalidate a measurement of the same code)."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2009_01177_amd", "csrc", "tor_schur.hip")
+    lines = []
+    for line in open(src):
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line:
+            lines.append(line)
+    return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
+
+
 def measured_traffic(tier: str, n: int, algo: str):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
-    import hashlib
+    counter summary, if it was taken on the current kernel code."""
     path = os.path.join(ROOT, "profiles", "leaf_kernel_n30_traffic.txt")
-    src = os.path.join(ROOT, "paper_2009_01177_amd", "csrc", "tor_schur.hip")
     if algo != "schur" or n != 30 or not os.path.exists(path):
         return None
     kv = {}
@@ -110,8 +123,7 @@ def measured_traffic(tier: str, n: int, algo: str):
         if "=" in line and not line.startswith("#"):
             k, v = line.strip().split("=", 1)
             kv[k] = v
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if kv.get("source_sha256_prefix") != sha:
+    if kv.get("code_sha256_prefix") != kernel_code_hash():
         return None
     v = kv.get(f"{tier}_traffic_bytes")
     return int(v) if v else None
