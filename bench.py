@@ -97,18 +97,26 @@ def paper_eq9_flops(n: int) -> float:
     return sum(math.comb(n, i) * (32.0 / 3 * i ** 3 + 4 * i * i - 8.0 / 3 * i) for i in range(1, n + 1))
 
 
-def kernel_code_hash() -> str:
-    """sha256 prefix of the Schur kernels' code (tor_schur.hip with its //
-    comments, trailing blanks and empty lines removed, so that a comment edit
-    does not invalidate a measurement of the same code)."""
+KERNEL_SOURCES = ("tor_schur.hip", "tiers.hpp", "prec.hpp", "tor_internal.hpp")
+
+
+def kernel_code_hash(texts=None) -> str:
+    """sha256 prefix of the Schur kernels' code: tor_schur.hip and the headers
+    it compiles from, with // comments, trailing blanks and empty lines
+    removed, so that a comment edit does not invalidate a measurement of the
+    same code.  `texts` (file name -> text) overrides reading the files."""
     import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2009_01177_amd", "csrc", "tor_schur.hip")
     lines = []
-    for line in open(src):
-        line = re.sub(r"//.*$", "", line).rstrip()
-        if line:
-            lines.append(line)
+    for name in KERNEL_SOURCES:
+        if texts is not None:
+            text = texts[name]
+        else:
+            text = open(os.path.join(ROOT, "paper_2009_01177_amd", "csrc", name)).read()
+        for line in text.splitlines():
+            line = re.sub(r"//.*$", "", line).rstrip()
+            if line:
+                lines.append(line)
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
