@@ -35,6 +35,7 @@ __all__ = [
     "click_submatrix", "workload", "batched_workload", "random_instance",
     "thermal_o", "squeezed_o", "lossy_squeezed_o", "tmsv_o", "direct_sum_o",
     "permute_and_phase_o", "interleave_perm", "WORKLOADS",
+    "MCMC", "mcmc_state", "mcmc_proposals", "mcmc_uniforms",
 ]
 
 
@@ -250,3 +251,51 @@ def random_instance(n: int, seed: int, M: int | None = None, r=(0.8, 1.6), eta=0
     O_full = o_from_sigma_q(sq)
     modes = np.sort(rng.choice(M, size=n, replace=False))
     return click_submatrix(O_full, modes)
+
+
+# --------------------------------------------------------------------------
+# Markov-chain sampler inputs.  A chain walks over N-click patterns of an
+# M-mode state; its proposals (uniform N-subsets of the modes, drawn without
+# regard to the chain) and its acceptance variates are random numbers the
+# sampler consumes, so they are generated here and passed in.
+# --------------------------------------------------------------------------
+
+MCMC = {
+    # 5 modes, 2 clicks: 10 patterns, small enough to enumerate
+    "mcmc_m5_n2": dict(M=5, N=2, sq=("uniform", 0.4, 1.2), eta=0.6, seed=21, pseed=121),
+    # 24 modes, 8 clicks: parity runs
+    "mcmc_m24_n8": dict(M=24, N=8, sq=("uniform", 0.6, 1.2), eta=0.4, seed=22, pseed=122),
+    # 24 modes, 14 clicks: several middle-level tiles per Torontonian
+    "mcmc_m24_n14": dict(M=24, N=14, sq=("uniform", 0.6, 1.2), eta=0.4, seed=22, pseed=123),
+    # 100 modes, 20 clicks: the throughput workload
+    "mcmc_m100_n20": dict(M=100, N=20, sq=("uniform", 0.8, 1.6), eta=0.3, seed=2, pseed=124),
+}
+
+
+def mcmc_state(name: str):
+    """(sigma_Q, O_full) of a named sampler workload's M-mode state."""
+    spec = MCMC[name]
+    key = (spec["M"], spec["sq"], spec["eta"], spec["seed"])
+    if key not in _STATE_CACHE:
+        _STATE_CACHE[key] = _state(spec)
+    return _STATE_CACHE[key]
+
+
+def mcmc_proposals(name: str, chains: int, steps: int) -> np.ndarray:
+    """steps x chains x N int32: for every step and chain an N-subset of the
+    M modes drawn uniformly, ascending."""
+    spec = MCMC[name]
+    M, N = spec["M"], spec["N"]
+    rng = np.random.Generator(np.random.PCG64(spec["pseed"]))
+    out = np.empty((int(steps), int(chains), N), dtype=np.int32)
+    for t in range(int(steps)):
+        keys = rng.random((int(chains), M))
+        out[t] = np.sort(np.argsort(keys, axis=1)[:, :N], axis=1)
+    return out
+
+
+def mcmc_uniforms(name: str, chains: int, steps: int) -> np.ndarray:
+    """steps x chains float64 in [0, 1): the acceptance variates."""
+    spec = MCMC[name]
+    rng = np.random.Generator(np.random.PCG64(spec["pseed"] + 1000))
+    return rng.random((int(steps), int(chains)))
