@@ -161,6 +161,43 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
                      const int32_t* tiers, double tau, const tor_options_t* opt, void* stream,
                      tor_result_t* out);
 
+/* Markov chains over N-click patterns: the independence Metropolis sampler
+ * the paper scores candidate patterns with, about a hundred per sample
+ * (Sec. 7.1.1), on the pattern probabilities of Eq. 1,
+ * p(S) = Tor(O_S) / sqrt(det Sigma_Q), where O_S keeps rows and columns k
+ * and M+k of the M-mode O for every clicked mode k.
+ * `chains` chains run side by side for `steps` steps.  Step t offers chain b
+ * the candidate proposals[t][b][0..N-1]; step 0 takes it, and at a later step
+ * a chain at pattern x moves to the candidate c when
+ *     uniforms[t][b] * Tor(O_x) < Tor(O_c),
+ * with both Torontonians' leading binary64 words and the product rounded to
+ * binary64 (the vacuum factor of Eq. 1 is common to every pattern and
+ * cancels).  With candidates drawn uniformly and u uniform in [0, 1) a chain
+ * moves with probability min(1, p(c)/p(x)).  The candidates do not depend
+ * on the chains, so all steps x chains of them are scored first, in batched
+ * evaluations (as tor_eval_batched, in chunks of at most 1 GiB of packed
+ * O_S; the environment variable TOR_MCMC_CHUNK caps the candidates per
+ * chunk further), and then one lane per chain takes its decisions in order.
+ *   O_full     device, complex128, 2M x 2M of the M-mode state, block order,
+ *              leading dimension ld >= 2M; only the lower triangle is read
+ *   M, N       1 <= M; 0 <= N <= min(M, TOR_NMAX) clicks per pattern
+ *   chains, steps  >= 1, chains * steps < 2^31
+ *   proposals  device, int32 [steps][chains][N]: each row's modes strictly
+ *              increasing in [0, M) (may be NULL when N = 0)
+ *   uniforms   device, double [steps][chains], each in [0, 1]
+ *   tier       TOR_FP64 / TOR_DD / TOR_QD, or TOR_AUTO with target `tau`
+ *   opt        NULL or knobs as tor_eval_batched (TOR_FLAG_GRAPH is ignored)
+ *   cand_out   device, tor_result_t [steps][chains]: each candidate's Tor
+ *   state_step device, int32 [steps][chains]: after step t chain b holds the
+ *              candidate of step state_step[t][b] (<= t)
+ * The library allocates the packed candidates and frees them before it
+ * returns.  Synchronous.  TOR_EINVAL when a candidate row or variate is out
+ * of range (checked on the device before anything is scored), TOR_ENOTPD when
+ * some I - O_S was not positive definite (outputs still written). */
+int tor_mcmc(const void* O_full, int32_t M, int64_t ld, int32_t N, int32_t chains, int32_t steps,
+             const int32_t* proposals, const double* uniforms, int32_t tier, double tau,
+             const tor_options_t* opt, void* stream, tor_result_t* cand_out, int32_t* state_step);
+
 /* Per-level sums L_m = sum over |Z| = m of det(I - O_Z)^(-1/2), m = 0..n
  * (the pieces Alg. 1's level loop adds up, each unsigned).
  *   out_levels  host, 4*(n+1) doubles: level m as an expansion at [4m..4m+3]

@@ -43,9 +43,15 @@ def pattern_o(O_full, modes) -> np.ndarray:
 
 def pattern_tor(O_full, modes, threads: int = 0) -> Fraction:
     """Tor(O_S) exactly as a Fraction (Eq. 2); Tor of no clicks is 1."""
+    return pattern_tor_abs(O_full, modes, threads)[0]
+
+
+def pattern_tor_abs(O_full, modes, threads: int = 0):
+    """(Tor(O_S), S_abs) as Fractions, S_abs the sum of the terms' magnitudes."""
     if len(modes) == 0:
-        return Fraction(1)
-    return _oracle_tor(pattern_o(O_full, modes), threads=threads)["tor"]
+        return Fraction(1), Fraction(1)
+    r = _oracle_tor(pattern_o(O_full, modes), threads=threads)
+    return r["tor"], r["abs_sum"]
 
 
 def pattern_probability(O_full, sigma_q, modes) -> float:
@@ -70,8 +76,9 @@ def mcmc(O_full, proposals, uniforms, threads: int = 0, cache: dict | None = Non
       tor         steps x chains float64: Tor of each candidate, rounded
       margin      steps x chains float64: |u Tor(O_x) - Tor(O_c)| / Tor(O_c)
                   of each decision (inf at step 0), how far it was from a tie
-      exact       {pattern tuple: Fraction} of every candidate scored
-    A pattern seen twice is scored once (cache).
+      exact       {pattern tuple: (Tor, S_abs) as Fractions} of every
+                  candidate scored
+    A pattern seen twice is scored once (cache, same layout as exact).
     """
     P = np.asarray(proposals)
     U = np.asarray(uniforms, dtype=np.float64)
@@ -83,8 +90,8 @@ def mcmc(O_full, proposals, uniforms, threads: int = 0, cache: dict | None = Non
         for b in range(chains):
             key = tuple(int(m) for m in P[t, b])
             if key not in exact:
-                exact[key] = pattern_tor(O_full, key, threads=threads)
-            tor[t, b] = float(exact[key])
+                exact[key] = pattern_tor_abs(O_full, key, threads=threads)
+            tor[t, b] = float(exact[key][0])
     state_step = np.zeros((steps, chains), dtype=np.int32)
     margin = np.full((steps, chains), np.inf)
     for b in range(chains):

@@ -22,6 +22,7 @@ TOR_FLAG_GRAPH = 2
 # Every symbol include/tor.h declares.
 EXPORTS = (
     "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval", "tor_eval_batched",
+    "tor_mcmc",
     "tor_debug_level_sums", "tor_debug_sampled_terms", "tor_last_kernel_ms",
     "tor_next_mask", "tor_kth_mask", "tor_plan_items",
     "tor_features", "tor_mlp_forward", "tor_mlp_grad", "tor_mlp_adam",
@@ -134,6 +135,9 @@ def lib():
     L.tor_eval_batched.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), i32,
                                    ctypes.POINTER(i32), ctypes.c_double, ctypes.POINTER(TorOptionsC),
                                    vp, vp]
+    L.tor_mcmc.restype = ctypes.c_int
+    L.tor_mcmc.argtypes = [vp, i32, i64, i32, i32, i32, vp, vp, i32, ctypes.c_double,
+                           ctypes.POINTER(TorOptionsC), vp, vp, vp]
     L.tor_debug_level_sums.restype = ctypes.c_int
     L.tor_debug_level_sums.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
     L.tor_debug_sampled_terms.restype = ctypes.c_int

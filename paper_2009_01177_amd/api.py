@@ -174,6 +174,44 @@ def tor_eval_batched(batch: "Batch", tiers=None, tau: float = 1e-3, graph: bool 
     return _results_from(batch.out[:B].cpu().numpy())
 
 
+def tor_mcmc(O_full, proposals, uniforms, tier="dd", tau: float = 1e-3, stream=None,
+             bottom_modes: int = 0):
+    """Markov chains over N-click patterns (include/tor.h, tor_mcmc).
+
+    O_full     2M x 2M complex O of the state (numpy or torch)
+    proposals  steps x chains x N int32 candidate modes, rows ascending
+    uniforms   steps x chains acceptance variates in [0, 1]
+    Returns (state_step, cand): device tensors, int32 [steps, chains] and
+    float64 [steps, chains, 8] holding one tor_result_t per candidate
+    (results_of() decodes them).  Synchronous."""
+    torch = _torch()
+    Od, M, ld = _device_o(O_full)
+    dev = Od.device
+    P = torch.as_tensor(proposals)
+    P = P.to(device=dev, dtype=torch.int32).contiguous()
+    U = torch.as_tensor(uniforms).to(device=dev, dtype=torch.float64).contiguous()
+    if P.dim() != 3 or U.dim() != 2 or tuple(P.shape[:2]) != tuple(U.shape):
+        raise ValueError("proposals must be steps x chains x N and uniforms steps x chains")
+    steps, chains, N = (int(x) for x in P.shape)
+    cand = torch.zeros((steps, chains, 8), dtype=torch.float64, device=dev)
+    state = torch.zeros((steps, chains), dtype=torch.int32, device=dev)
+    opt = _lib.TorOptionsC(_lib.TOR_ALGO_AUTO, -1, 0, 0, int(bottom_modes))
+    rc = lib().tor_mcmc(ctypes.c_void_p(Od.data_ptr()), M, ld, N, chains, steps,
+                        ctypes.c_void_p(P.data_ptr()), ctypes.c_void_p(U.data_ptr()), tier_id(tier),
+                        float(tau), ctypes.byref(opt), _stream_ptr(stream),
+                        ctypes.c_void_p(cand.data_ptr()), ctypes.c_void_p(state.data_ptr()))
+    check(rc, "tor_mcmc")
+    return state, cand
+
+
+def results_of(cand) -> list:
+    """Decode tor_result_t records (a [..., 8] float64 tensor or array) into
+    a flat list of TorResult."""
+    if hasattr(cand, "cpu"):
+        cand = cand.cpu().numpy()
+    return _results_from(np.asarray(cand).reshape(-1, 8))
+
+
 def tor_autotune(n: int, tier="dd", stream=None):
     """(best s_b, times in ms for s_b = 1..5, -1 where not run)."""
     best = ctypes.c_int32(0)

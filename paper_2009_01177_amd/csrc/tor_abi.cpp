@@ -973,6 +973,68 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   return TOR_OK;
 }
 
+int tor_mcmc(const void* O_full, int32_t M, int64_t ld, int32_t N, int32_t chains, int32_t steps,
+             const int32_t* proposals, const double* uniforms, int32_t tier, double tau,
+             const tor_options_t* opt, void* stream, tor_result_t* cand_out, int32_t* state_step) {
+  if (M < 1 || N < 0 || N > M || N > TOR_NMAX || chains < 1 || steps < 1) return TOR_EINVAL;
+  if (ld < 2 * (int64_t)M) return TOR_EINVAL;
+  if (!O_full || !uniforms || !cand_out || !state_step || (N > 0 && !proposals)) return TOR_EINVAL;
+  if (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD && tier != TOR_AUTO) return TOR_EINVAL;
+  if (tier == TOR_AUTO && !(tau > 0.0)) return TOR_EINVAL;
+  if (opt && opt->algo != TOR_ALGO_AUTO && opt->algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
+  const int64_t total = (int64_t)chains * steps;
+  if (total > INT32_MAX) return TOR_EINVAL;
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  // candidates are scored in chunks of at most 1 GiB of packed O_S
+  const int64_t per = 4 * (int64_t)N * N;  // complex elements per candidate
+  int64_t chunk = total;
+  if (per > 0) chunk = std::min<int64_t>(chunk, std::max<int64_t>(1, ((int64_t)1 << 26) / per));
+  if (const char* e = getenv("TOR_MCMC_CHUNK")) {
+    const long long c = atoll(e);
+    if (c >= 1) chunk = std::min<int64_t>(chunk, c);
+  }
+  char* buf = nullptr;
+  TOR_HIP(hipMalloc((void**)&buf, 256 + (size_t)(per > 0 ? chunk * per : 1) * sizeof(double2)));
+  int32_t* flag = (int32_t*)buf;
+  double2* packed = (double2*)(buf + 256);
+  int32_t hflag = 0;
+  auto read_flag = [&]() -> int {
+    TOR_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TOR_HIP(hipStreamSynchronize(s));
+    return TOR_OK;
+  };
+  auto run = [&]() -> int {
+    TOR_HIP(launch_zero_words((uint32_t*)flag, 1, s));
+    TOR_HIP(launch_mcmc_check(proposals, uniforms, total, N, M, flag, s));
+    TOR_TRY(read_flag());
+    if (hflag) return TOR_EINVAL;
+    tor_options_t o;
+    memset(&o, 0, sizeof(o));
+    o.algo = TOR_ALGO_AUTO;
+    o.split_depth = -1;
+    if (opt) o = *opt;
+    o.flags &= ~TOR_FLAG_GRAPH;  // every chunk has its own output range
+    std::vector<int64_t> offs((size_t)chunk);
+    std::vector<int32_t> ns((size_t)chunk, N), ts((size_t)chunk, tier);
+    for (int64_t k = 0; k < chunk; ++k) offs[(size_t)k] = k * per;
+    for (int64_t c0 = 0; c0 < total; c0 += chunk) {
+      const int cnt = (int)std::min<int64_t>(chunk, total - c0);
+      TOR_HIP(launch_mcmc_gather((const double2*)O_full, ld, M, proposals, N, c0, cnt, packed, s));
+      TOR_TRY(tor_eval_batched(packed, offs.data(), ns.data(), cnt, ts.data(), tau, &o, stream,
+                               cand_out + c0));
+    }
+    TOR_HIP(launch_mcmc_scan(cand_out, uniforms, chains, steps, state_step, flag, s));
+    TOR_TRY(read_flag());
+    return hflag & 4 ? TOR_ENOTPD : TOR_OK;
+  };
+  const int rc = run();
+  (void)hipStreamSynchronize(s);  // nothing may still read the buffer
+  (void)hipFree(buf);
+  return rc;
+}
+
 int tor_select_tiers(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
                      double tau, void* stream, int32_t* tiers, double* log10_kappa,
                      int32_t* source) {

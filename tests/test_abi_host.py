@@ -98,3 +98,28 @@ def test_autotune_table_round_trip_needs_no_gpu(tmp_path):
     bad.write_text("30 7 3\n")
     with pytest.raises(tor.TorError):
         tor.tor_autotune_load(str(bad))
+
+
+def test_mcmc_argument_checks_need_no_gpu(L):
+    from paper_2009_01177_amd import _lib
+    d = ctypes.c_void_p(16)
+    ok = dict(O=d, M=6, ld=12, N=2, chains=4, steps=3, P=d, U=d, tier=_lib.TOR_DD, tau=1e-3,
+              out=d, st=d)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.tor_mcmc(a["O"], a["M"], a["ld"], a["N"], a["chains"], a["steps"], a["P"], a["U"],
+                          a["tier"], a["tau"], None, None, a["out"], a["st"])
+
+    E = _lib.TOR_EINVAL
+    assert call(M=0) == E
+    assert call(N=7) == E                      # more clicks than modes
+    assert call(N=-1) == E
+    assert call(M=100, ld=200, N=_lib.TOR_NMAX + 1) == E
+    assert call(ld=11) == E                    # ld < 2M
+    assert call(chains=0) == E and call(steps=0) == E
+    assert call(chains=1 << 16, steps=1 << 15) == E   # chains * steps >= 2^31
+    assert call(O=None) == E and call(U=None) == E and call(out=None) == E and call(st=None) == E
+    assert call(P=None) == E                   # candidates needed when N > 0
+    assert call(tier=5) == E
+    assert call(tier=_lib.TOR_AUTO, tau=0.0) == E
