@@ -239,6 +239,41 @@ def batched_leg(tor, count: int, tau: float, steps: int, check: bool):
     return out
 
 
+def mcmc_leg(tor, chains: int, steps: int, reps: int):
+    """Sampler workload: `chains` independence Metropolis chains over
+    20-click patterns of a 100-mode lossy state, `steps` steps each (every
+    step scores one candidate per chain), through tor_mcmc in double-double
+    with the state, candidates and variates resident on the device."""
+    import numpy as np
+    import torch
+    import gbs_inputs as g
+    name = "mcmc_m100_n20"
+    spec = g.MCMC[name]
+    sq, O = g.mcmc_state(name)
+    Od = torch.from_numpy(O).to("cuda:0")
+    P = torch.from_numpy(g.mcmc_proposals(name, chains, steps)).to("cuda:0")
+    U = torch.from_numpy(g.mcmc_uniforms(name, chains, steps)).to("cuda:0")
+    tor.tor_mcmc(Od, P, U, tier="dd")  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        state, cand = tor.tor_mcmc(Od, P, U, tier="dd")
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / reps
+    S = state.cpu().numpy()
+    moves = float((S[1:] == np.arange(1, steps)[:, None]).mean()) if steps > 1 else 0.0
+    ncand = chains * steps
+    out = {"workload": f"{chains} chains x {steps} steps over {spec['N']}-click patterns of a "
+                       f"{spec['M']}-mode lossy GBS state (Haar U, r~U[0.8,1.6], eta=0.3), "
+                       f"uniform candidates", "tier": "dd", "chains": chains, "steps": steps,
+           "candidates": ncand, "s": sec, "candidates_per_s": ncand / sec,
+           "terms_per_s": ncand * float(1 << spec["N"]) / sec,
+           "samples_per_s_at_100_candidates": ncand / sec / 100.0, "move_fraction": moves}
+    print(f"[bench] mcmc: {sec * 1e3:.1f} ms for {ncand} candidates, {ncand / sec:.0f} candidates/s",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +292,9 @@ def main():
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-check", action="store_true", help="check the batched leg against QD")
+    ap.add_argument("--mcmc-chains", type=int, default=1024, help="sampler leg chains (0: skip)")
+    ap.add_argument("--mcmc-steps", type=int, default=16)
+    ap.add_argument("--mcmc-reps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first copy this many bytes device-to-device (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -343,6 +381,8 @@ def main():
     }
     if args.batch > 0:
         line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check)
+    if args.mcmc_chains > 0:
+        line["mcmc"] = mcmc_leg(tor, args.mcmc_chains, args.mcmc_steps, args.mcmc_reps)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(O, n, args.cpu_seconds)

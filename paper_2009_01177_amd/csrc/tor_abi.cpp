@@ -20,6 +20,7 @@
 #include "../../include/tor.h"
 #include "tor_host.h"
 #include "tor_internal.hpp"
+#include "tor_mcmc.hpp"
 
 namespace tor {
 namespace {

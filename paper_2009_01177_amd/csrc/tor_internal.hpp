@@ -86,19 +86,6 @@ hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* 
                        int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st);
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu);
 
-// ---- Markov-chain sampler kernels (tor_mcmc.hip) ----
-// flag |= 1 for a candidate row not strictly increasing in [0, M), 2 for a
-// variate outside [0, 1]; count rows of N int32 and count variates.
-hipError_t launch_mcmc_check(const int32_t* prop, const double* u, int64_t count, int N, int M,
-                             int32_t* flag, hipStream_t s);
-// O_S of candidates first .. first+count-1 into out (2N x 2N each, packed).
-hipError_t launch_mcmc_gather(const double2* O, int64_t ld, int M, const int32_t* prop, int N,
-                              int64_t first, int count, double2* out, hipStream_t s);
-// Move decisions of `chains` chains over `steps` steps; flag |= 4 when a
-// candidate's status is not TOR_OK.
-hipError_t launch_mcmc_scan(const tor_result_t* cand, const double* u, int chains, int steps,
-                            int32_t* state_step, int32_t* flag, hipStream_t s);
-
 // ---- selector kernels (tor_select.hip) ----
 size_t features_lds_bytes(int nmax);
 hipError_t launch_features(const double2* O, const int64_t* offs, const int32_t* ns, int batch,

@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include "tor_internal.hpp"
+#include "tor_mcmc.hpp"
 
 namespace tor {
 namespace {
