@@ -295,6 +295,8 @@ def main():
     ap.add_argument("--mcmc-chains", type=int, default=1024, help="sampler leg chains (0: skip)")
     ap.add_argument("--mcmc-steps", type=int, default=16)
     ap.add_argument("--mcmc-reps", type=int, default=2)
+    ap.add_argument("--mcmc-only", action="store_true",
+                    help="run only the sampler leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first copy this many bytes device-to-device (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -317,6 +319,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.mcmc_only:
+        print(json.dumps({"mcmc": mcmc_leg(tor, max(args.mcmc_chains, 1), args.mcmc_steps,
+                                           args.mcmc_reps)}), flush=True)
+        return
 
     n = args.n
     O, modes = g.workload("n30_lossy", n=n)
