@@ -401,6 +401,20 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
   if ((size_t)grid > p.mids) grid = (int)p.mids;
 
   TOR_HIP(launch_zero_words(cnt, 64, s));
+  // levels a launch takes from states of `modes` modes, at most `left`:
+  // up to three at once where their intermediate states fit in LDS
+  auto levels_at = [&](int modes, int left) {
+    for (int k = std::min(3, left); k >= 2; --k) {
+      const size_t b = expand_multi_lds_bytes(tier, modes, k);
+      if (b > 0 && b <= EXPAND_MULTI_LDS_MAX) return k;
+    }
+    return 1;
+  };
+  auto expand_levels = [&](const void* im, const void* ig, const int32_t* in_, int modes, int K, int nst,
+                           void* om, void* og, int32_t* on) {
+    if (K == 1) return launch_expand(tier, im, ig, in_, modes, nst, om, og, on, status, s);
+    return launch_expand_multi(tier, im, ig, in_, modes, K, nst, om, og, on, status, s);
+  };
   // stage 0: roots, then breadth-first to depth D_s into the kept buffer
   {
     int cur = 0;
@@ -409,14 +423,16 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
     void* dg = direct ? (void*)(B + p.o_rg) : (void*)(B + p.o_g[0]);
     int32_t* dn = direct ? (int32_t*)(B + p.o_rn) : (int32_t*)(B + p.o_n[0]);
     TOR_HIP(launch_real_root(tier, (const double2*)O, offs_dev, p.R, n, ld, dm, dg, dn, s));
-    for (int j = 0; j < p.D_s; ++j) {
-      const bool last = (j == p.D_s - 1);
+    for (int j = 0; j < p.D_s;) {
+      const int K = levels_at(n - j, p.D_s - j);
+      const bool last = (j + K == p.D_s);
       void* om = last ? (void*)(B + p.o_rm) : (void*)(B + p.o_m[1 - cur]);
       void* og = last ? (void*)(B + p.o_rg) : (void*)(B + p.o_g[1 - cur]);
       int32_t* on = last ? (int32_t*)(B + p.o_rn) : (int32_t*)(B + p.o_n[1 - cur]);
-      TOR_HIP(launch_expand(tier, B + p.o_m[cur], B + p.o_g[cur], (const int32_t*)(B + p.o_n[cur]),
-                            n - j, p.R << j, om, og, on, status, s));
+      TOR_HIP(expand_levels(B + p.o_m[cur], B + p.o_g[cur], (const int32_t*)(B + p.o_n[cur]), n - j, K,
+                            p.R << j, om, og, on));
       cur = 1 - cur;
+      j += K;
     }
   }
   const size_t rb = p.rb, ab = p.ab;
@@ -427,13 +443,15 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
     const char* ig = B + p.o_rg + rb * first;
     const int32_t* in_ = (const int32_t*)(B + p.o_rn) + first;
     int cur = -1;  // -1: the chunk's depth-D_s states themselves
-    for (int j = 0; j < p.Dl; ++j) {
+    for (int j = 0; j < p.Dl;) {
       const int nx = (cur == 0) ? 1 : 0;
-      TOR_HIP(launch_expand(tier, cur < 0 ? (const void*)im : (const void*)(B + p.o_m[cur]),
+      const int K = levels_at(n - p.D_s - j, p.Dl - j);
+      TOR_HIP(expand_levels(cur < 0 ? (const void*)im : (const void*)(B + p.o_m[cur]),
                             cur < 0 ? (const void*)ig : (const void*)(B + p.o_g[cur]),
-                            cur < 0 ? in_ : (const int32_t*)(B + p.o_n[cur]), n - p.D_s - j, cr << j,
-                            B + p.o_m[nx], B + p.o_g[nx], (int32_t*)(B + p.o_n[nx]), status, s));
+                            cur < 0 ? in_ : (const int32_t*)(B + p.o_n[cur]), n - p.D_s - j, K, cr << j,
+                            B + p.o_m[nx], B + p.o_g[nx], (int32_t*)(B + p.o_n[nx])));
       cur = nx;
+      j += K;
     }
     const void* lm = cur < 0 ? (const void*)im : (const void*)(B + p.o_m[cur]);
     const void* lg = cur < 0 ? (const void*)ig : (const void*)(B + p.o_g[cur]);

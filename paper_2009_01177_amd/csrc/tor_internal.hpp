@@ -82,6 +82,15 @@ hipError_t launch_real_root(int tier, const double2* O, const int64_t* offs, int
 hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
                          int s, int nst, void* out_mat, void* out_g, int32_t* out_m,
                          int32_t* status, hipStream_t st);
+// K = 2 or 3 expansions in one launch (the levels in between in LDS): nst
+// states of s modes -> nst * 2^K states of s - K modes, numbered as K
+// launch_expand calls would number them, with the same values.  0 bytes:
+// not available for these arguments; launches need bytes <= EXPAND_MULTI_LDS_MAX.
+constexpr size_t EXPAND_MULTI_LDS_MAX = 48 * 1024;
+size_t expand_multi_lds_bytes(int tier, int s, int K);
+hipError_t launch_expand_multi(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
+                               int s, int K, int nst, void* out_mat, void* out_g, int32_t* out_m,
+                               int32_t* status, hipStream_t st);
 hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
                        int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st);
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu);

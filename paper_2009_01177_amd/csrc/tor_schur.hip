@@ -247,52 +247,170 @@ __global__ void real_root_kernel(const double2* __restrict__ O, const int64_t* _
 // Top level: expand every state of a frontier by one mode.
 // in: nst states of s modes; out: 2*nst states of s-1 modes,
 // child 2z leaves the mode out, child 2z+1 takes it in.
+// G states per 256-thread workgroup, 256/G threads each: every thread forms
+// its state's pivot itself (the same operations, so the same values), the
+// pivot column goes through LDS, and one barrier separates it from the
+// entry updates.  Many small states (the deep levels) take G = 4; the few
+// large ones near the root take G = 1.
 // --------------------------------------------------------------------------
 
-template <class TT>
+template <class TT, int G>
 __global__ __launch_bounds__(256) void expand_kernel(const typename TT::R* __restrict__ in_mat,
                                                      const typename TT::R* __restrict__ in_g,
-                                                     const int32_t* __restrict__ in_m, int s,
+                                                     const int32_t* __restrict__ in_m, int s, int nst,
                                                      typename TT::R* __restrict__ out_mat,
                                                      typename TT::R* __restrict__ out_g,
                                                      int32_t* __restrict__ out_m,
                                                      int32_t* __restrict__ status) {
   using R = typename TT::R;
-  __shared__ R su0[128], su1[128];
-  __shared__ R spv[3];
-  const int z = blockIdx.x;
-  const R* T = in_mat + (size_t)z * psize(s);
+  constexpr int TPS = 256 / G;  // threads per state
+  __shared__ R su0[G][128], su1[G][128];
+  const int grp = (int)threadIdx.x / TPS, t = (int)threadIdx.x % TPS;
+  const int z = (int)blockIdx.x * G + grp;
+  const bool live = z < nst;
+  const int zc = live ? z : nst - 1;  // a group past the end works on the last state, stores nothing
+  const R* T = in_mat + (size_t)zc * psize(s);
   const int sc = s - 1;
   const int nr = 2 * sc;  // rows of a child
-  if (threadIdx.x == 0) {
-    const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+  const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+  if (live && t == 0) {
     if (!pv.ok) atomicOr(status, 1);
-    spv[0] = pv.rl0;
-    spv[1] = pv.l10;
-    spv[2] = pv.rl1;
-    out_g[2 * z] = in_g[z];
+    const R g = in_g[z];
+    out_g[2 * z] = g;
     out_m[2 * z] = in_m[z];
-    out_g[2 * z + 1] = r_mul(r_mul(in_g[z], pv.rl0), pv.rl1);
+    out_g[2 * z + 1] = r_mul(r_mul(g, pv.rl0), pv.rl1);
     out_m[2 * z + 1] = in_m[z] + 1;
   }
-  __syncthreads();
-  for (int a = threadIdx.x; a < nr; a += blockDim.x) {
-    const R u0 = r_mul(T[pk(a + 2, 0)], spv[0]);
-    su0[a] = u0;
-    su1[a] = r_mul(r_fms(T[pk(a + 2, 1)], u0, spv[1]), spv[2]);
+  for (int a = t; a < nr; a += TPS) {
+    const R u0 = r_mul(T[pk(a + 2, 0)], pv.rl0);
+    su0[grp][a] = u0;
+    su1[grp][a] = r_mul(r_fms(T[pk(a + 2, 1)], u0, pv.l10), pv.rl1);
   }
   __syncthreads();
+  if (!live) return;
   R* ex = out_mat + (size_t)(2 * z) * psize(sc);
   R* in = out_mat + (size_t)(2 * z + 1) * psize(sc);
   const int ne = psize(sc);
-  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+  for (int e = t; e < ne; e += TPS) {
     int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
     while (pk(a + 1, 0) <= e) ++a;
     while (pk(a, 0) > e) --a;
     const int b = e - pk(a, 0);
-    const R t = T[pk(a + 2, b + 2)];
-    ex[e] = t;
-    in[e] = r_fms2(t, su0[a], su0[b], su1[a], su1[b]);
+    const R tv = T[pk(a + 2, b + 2)];
+    ex[e] = tv;
+    in[e] = r_fms2(tv, su0[grp][a], su0[grp][b], su1[grp][a], su1[grp][b]);
+  }
+}
+
+// Several top levels in one launch: one workgroup takes a state of s modes
+// K levels down, the levels in between in LDS, and writes its 2^K
+// descendants (descendant w = the decisions c1 .. cK as bits, c1 the most
+// significant, as K single-level expansions would number them).  The
+// operations and their operands are those of expand_kernel, so the
+// descendants are bit-for-bit the same; only the intermediate states stay
+// out of HBM.  LDS (dynamic, expand_multi_lds_bytes): the states of levels
+// 1 .. K-1, the pivot column of the widest level, pivots, g and |Z|.
+__host__ __device__ inline size_t expand_multi_vals(int s, int K) {
+  size_t v = 0;
+  for (int j = 1; j < K; ++j) v += ((size_t)1 << j) * psize(s - j);
+  size_t u = 0;
+  for (int j = 0; j < K; ++j) {
+    const size_t w = ((size_t)1 << j) * 2 * (s - j - 1);
+    u = u > w ? u : w;
+  }
+  return v + 2 * u + 3 * ((size_t)1 << (K - 1)) + 2 * ((size_t)1 << K);
+}
+
+template <class TT>
+__global__ __launch_bounds__(256) void expand_multi_kernel(const typename TT::R* __restrict__ in_mat,
+                                                           const typename TT::R* __restrict__ in_g,
+                                                           const int32_t* __restrict__ in_m, int s, int K,
+                                                           typename TT::R* __restrict__ out_mat,
+                                                           typename TT::R* __restrict__ out_g,
+                                                           int32_t* __restrict__ out_m,
+                                                           int32_t* __restrict__ status) {
+  using R = typename TT::R;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* lds = reinterpret_cast<R*>(smem_raw);
+  const int z = blockIdx.x;
+  const int tid = (int)threadIdx.x;
+  // carve: level states (1 .. K-1), u0 | u1, pivots, g; then |Z| as int32
+  size_t off = 0;
+  R* lvl[3] = {nullptr, nullptr, nullptr};
+  for (int j = 1; j < K; ++j) {
+    lvl[j] = lds + off;
+    off += ((size_t)1 << j) * psize(s - j);
+  }
+  size_t umax = 0;
+  for (int j = 0; j < K; ++j) {
+    const size_t w = ((size_t)1 << j) * 2 * (s - j - 1);
+    umax = umax > w ? umax : w;
+  }
+  R* su0 = lds + off;
+  R* su1 = su0 + umax;
+  R* spv = su1 + umax;                  // 3 per state of the widest level
+  R* sg = spv + 3 * (1 << (K - 1));     // g of two consecutive levels, 2^K entries each
+  int32_t* sm = reinterpret_cast<int32_t*>(sg + 2 * (1 << K));  // |Z|, likewise
+  const R* T0 = in_mat + (size_t)z * psize(s);
+  for (int j = 0; j < K; ++j) {
+    const int sj = s - j;                // modes of the states of level j
+    const int nsj = 1 << j;
+    const int nr = 2 * (sj - 1);
+    const int ne = psize(sj - 1);
+    const bool last = (j == K - 1);
+    const R* src = j == 0 ? T0 : lvl[j];
+    const int ps = psize(sj);
+    // pivots and the children's g and |Z|
+    if (tid < nsj) {
+      const R* T = src + (size_t)tid * ps;
+      const Pivot<R> pv = make_pivot(T[pk(0, 0)], T[pk(1, 0)], T[pk(1, 1)]);
+      if (!pv.ok) atomicOr(status, 1);
+      spv[3 * tid] = pv.rl0;
+      spv[3 * tid + 1] = pv.l10;
+      spv[3 * tid + 2] = pv.rl1;
+      const int cur = (j & 1) << K, nxt = ((j + 1) & 1) << K;
+      const R g = j == 0 ? in_g[z] : sg[cur + tid];
+      const int32_t m = j == 0 ? in_m[z] : sm[cur + tid];
+      const R gi = r_mul(r_mul(g, pv.rl0), pv.rl1);
+      if (last) {
+        const size_t w = ((size_t)z << K) + 2 * tid;
+        out_g[w] = g;
+        out_m[w] = m;
+        out_g[w + 1] = gi;
+        out_m[w + 1] = m + 1;
+      } else {
+        sg[nxt + 2 * tid] = g;
+        sm[nxt + 2 * tid] = m;
+        sg[nxt + 2 * tid + 1] = gi;
+        sm[nxt + 2 * tid + 1] = m + 1;
+      }
+    }
+    __syncthreads();
+    // pivot columns
+    for (int idx = tid; idx < nsj * nr; idx += 256) {
+      const int st = idx / nr, a = idx - st * nr;
+      const R* T = src + (size_t)st * ps;
+      const R u0 = r_mul(T[pk(a + 2, 0)], spv[3 * st]);
+      su0[idx] = u0;
+      su1[idx] = r_mul(r_fms(T[pk(a + 2, 1)], u0, spv[3 * st + 1]), spv[3 * st + 2]);
+    }
+    __syncthreads();
+    // entries of both children of every state
+    R* dst = last ? out_mat + ((size_t)z << K) * ne : lvl[j + 1];
+    for (int idx = tid; idx < nsj * ne; idx += 256) {
+      const int st = idx / ne, e = idx - st * ne;
+      int a = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+      while (pk(a + 1, 0) <= e) ++a;
+      while (pk(a, 0) > e) --a;
+      const int b = e - pk(a, 0);
+      const R* T = src + (size_t)st * ps;
+      const R* u0 = su0 + st * nr;
+      const R* u1 = su1 + st * nr;
+      const R tv = T[pk(a + 2, b + 2)];
+      dst[(size_t)(2 * st) * ne + e] = tv;
+      dst[(size_t)(2 * st + 1) * ne + e] = r_fms2(tv, u0[a], u0[b], u1[a], u1[b]);
+    }
+    __syncthreads();
   }
 }
 
@@ -813,23 +931,65 @@ hipError_t launch_real_root(int tier, const double2* O, const int64_t* offs, int
   return hipGetLastError();
 }
 
+// Frontier sizes from which the expansion packs two or four states into a
+// workgroup.
+constexpr int EXPAND_G2_MIN = 512;
+constexpr int EXPAND_G4_MIN = 2048;
+
 hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
                          int s, int nst, void* out_mat, void* out_g, int32_t* out_m,
                          int32_t* status, hipStream_t st) {
   if (nst <= 0) return hipSuccess;
+  // states per workgroup: enough workgroups to fill the chip several times
+  // over with the fewest threads idle on small states
+  const int G = nst >= EXPAND_G4_MIN ? 4 : (nst >= EXPAND_G2_MIN ? 2 : 1);
+  const dim3 grid((nst + G - 1) / G), block(256);
+  switch (tier * 4 + G) {
+#define TOR_EXPAND_CASE(TID, TT, RT, GG)                                                                \
+  case TID * 4 + GG:                                                                                   \
+    hipLaunchKernelGGL((expand_kernel<TT, GG>), grid, block, 0, st, (const RT*)in_mat, (const RT*)in_g, \
+                       in_m, s, nst, (RT*)out_mat, (RT*)out_g, out_m, status);                         \
+    break;
+    TOR_EXPAND_CASE(TOR_FP64, TierF64, double, 1)
+    TOR_EXPAND_CASE(TOR_FP64, TierF64, double, 2)
+    TOR_EXPAND_CASE(TOR_FP64, TierF64, double, 4)
+    TOR_EXPAND_CASE(TOR_DD, TierDD, dd, 1)
+    TOR_EXPAND_CASE(TOR_DD, TierDD, dd, 2)
+    TOR_EXPAND_CASE(TOR_DD, TierDD, dd, 4)
+    TOR_EXPAND_CASE(TOR_QD, TierQD, qd, 1)
+    TOR_EXPAND_CASE(TOR_QD, TierQD, qd, 2)
+    TOR_EXPAND_CASE(TOR_QD, TierQD, qd, 4)
+#undef TOR_EXPAND_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t expand_multi_lds_bytes(int tier, int s, int K) {
+  if (K < 2 || K > 3 || s - K < 1) return 0;
+  return expand_multi_vals(s, K) * schur_value_bytes(tier) + 2 * ((size_t)1 << K) * sizeof(int32_t);
+}
+
+hipError_t launch_expand_multi(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
+                               int s, int K, int nst, void* out_mat, void* out_g, int32_t* out_m,
+                               int32_t* status, hipStream_t st) {
+  if (nst <= 0) return hipSuccess;
+  const size_t lds = expand_multi_lds_bytes(tier, s, K);
+  if (lds == 0 || lds > EXPAND_MULTI_LDS_MAX) return hipErrorInvalidValue;
   const dim3 grid(nst), block(256);
   switch (tier) {
     case TOR_FP64:
-      hipLaunchKernelGGL(expand_kernel<TierF64>, grid, block, 0, st, (const double*)in_mat,
-                         (const double*)in_g, in_m, s, (double*)out_mat, (double*)out_g, out_m, status);
+      hipLaunchKernelGGL(expand_multi_kernel<TierF64>, grid, block, lds, st, (const double*)in_mat,
+                         (const double*)in_g, in_m, s, K, (double*)out_mat, (double*)out_g, out_m, status);
       break;
     case TOR_DD:
-      hipLaunchKernelGGL(expand_kernel<TierDD>, grid, block, 0, st, (const dd*)in_mat,
-                         (const dd*)in_g, in_m, s, (dd*)out_mat, (dd*)out_g, out_m, status);
+      hipLaunchKernelGGL(expand_multi_kernel<TierDD>, grid, block, lds, st, (const dd*)in_mat,
+                         (const dd*)in_g, in_m, s, K, (dd*)out_mat, (dd*)out_g, out_m, status);
       break;
     default:
-      hipLaunchKernelGGL(expand_kernel<TierQD>, grid, block, 0, st, (const qd*)in_mat,
-                         (const qd*)in_g, in_m, s, (qd*)out_mat, (qd*)out_g, out_m, status);
+      hipLaunchKernelGGL(expand_multi_kernel<TierQD>, grid, block, lds, st, (const qd*)in_mat,
+                         (const qd*)in_g, in_m, s, K, (qd*)out_mat, (qd*)out_g, out_m, status);
   }
   return hipGetLastError();
 }
