@@ -72,6 +72,26 @@ def test_chains_match_reference_n14_several_tiles(tor):
     _check_against_reference(tor, "mcmc_m24_n14", 8, 6, "dd")
 
 
+def test_chains_with_selected_tiers(tor):
+    # TOR_AUTO: each candidate gets the cheapest tier the selector expects to
+    # meet tau (relative to |Tor|); the seeded decisions are further from a
+    # tie than 1e-4, so tau = 1e-8 leaves the chains unchanged
+    tau = 1e-8
+    O, P, U, ref = _reference("mcmc_m24_n8", 64, 24)
+    print("[mcmc] mcmc_m24_n8 chains=64 steps=24 tier=auto", flush=True)
+    state, cand = tor.tor_mcmc(O, P, U, tier="auto", tau=tau)
+    used = set()
+    for k, r in enumerate(tor.results_of(cand)):
+        t, b = divmod(k, 64)
+        exact = ref["exact"][tuple(int(m) for m in P[t, b])][0]
+        assert r.status == 0
+        used.add(r.tier_used)
+        assert float(abs(r.exact - exact) / abs(exact)) <= 10 * tau
+    assert used <= {tor.TOR_FP64, tor.TOR_DD, tor.TOR_QD}
+    assert float(np.min(ref["margin"][1:])) > 1e-4
+    assert np.array_equal(state.cpu().numpy(), ref["state_step"])
+
+
 def test_chunked_scoring_gives_the_same_chains(tor, monkeypatch):
     O, P, U, ref = _reference("mcmc_m24_n8", 64, 24)
     state0, cand0 = tor.tor_mcmc(O, P, U, tier="dd")
