@@ -183,7 +183,7 @@ def cpu_baseline(O, n, seconds: float):
                        f"binary128 per-subset Cholesky, {dt:.1f} s on {threads} threads")
 
 
-def batched_leg(tor, count: int, tau: float, steps: int, check: bool):
+def batched_leg(tor, count: int, tau: float, steps: int, check: bool, extra_taus=()):
     """Batched workload: `count` click patterns (n ~ U{8..24}) of one 100-mode
     lossy state; solves/s for fixed DD (graph replay) and for the learned
     selector (TOR_AUTO: features, network, evaluation, spot re-evaluation)."""
@@ -224,6 +224,7 @@ def batched_leg(tor, count: int, tau: float, steps: int, check: bool):
     out["gain_learned_vs_bounds_only"] = s_fb / s_ml
     print(f"[bench] batched auto: bounds-only {s_fb * 1e3:.1f} ms, learned {s_ml * 1e3:.1f} ms "
           f"({st_ml})", file=sys.stderr, flush=True)
+    ref = None
     if check:
         res = tor.tor_eval_batched(b, tau=tau)
         ref = tor.tor_eval_batched(b, tiers="qd")
@@ -236,6 +237,25 @@ def batched_leg(tor, count: int, tau: float, steps: int, check: bool):
                 worst = max(worst, float(abs(r.exact - tq) / abs(tq)))
                 worst_dd = max(worst_dd, float(abs(d.exact - tq) / abs(tq)))
         out["max_rel_err_vs_qd"] = {"auto_learned": worst, "fixed_dd": worst_dd}
+    # the same comparison at further accuracy targets (one timed call of the
+    # bound-estimate-only selector each: it is the slow one)
+    for t2 in extra_taus:
+        tor.tor_selector_set(None)
+        s_fb2 = timed(lambda: tor.tor_eval_batched(b, tau=t2, graph=True, sync=False), 1)
+        st_fb2 = tor.tor_last_select_stats()
+        selector.load_default()
+        s_ml2 = timed(lambda: tor.tor_eval_batched(b, tau=t2, graph=True, sync=False), steps)
+        st_ml2 = tor.tor_last_select_stats()
+        row = {"auto_bounds_only": {"s": s_fb2, "stats": st_fb2},
+               "auto_learned": {"s": s_ml2, "solves_per_s": count / s_ml2, "stats": st_ml2},
+               "gain_learned_vs_fixed_dd": s_dd / s_ml2, "gain_learned_vs_bounds_only": s_fb2 / s_ml2}
+        if check:
+            res2 = tor.tor_eval_batched(b, tau=t2)
+            row["max_rel_err_vs_qd"] = max(float(abs(r.exact - q.exact) / abs(q.exact))
+                                           for r, q in zip(res2, ref) if q.exact != 0)
+        out.setdefault("by_tau", {})[repr(t2)] = row
+        print(f"[bench] batched tau={t2:g}: learned {s_ml2 * 1e3:.1f} ms ({st_ml2}), bounds-only "
+              f"{s_fb2 * 1e3:.1f} ms", file=sys.stderr, flush=True)
     return out
 
 
@@ -292,6 +312,8 @@ def main():
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--batch-check", action="store_true", help="check the batched leg against QD")
+    ap.add_argument("--batch-taus", default="",
+                    help="further accuracy targets for the batched leg, comma-separated (e.g. 1e-4,1e-6)")
     ap.add_argument("--mcmc-chains", type=int, default=1024, help="sampler leg chains (0: skip)")
     ap.add_argument("--mcmc-steps", type=int, default=16)
     ap.add_argument("--mcmc-reps", type=int, default=2)
@@ -387,7 +409,8 @@ def main():
         if algo == "schur" else flops,
     }
     if args.batch > 0:
-        line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check)
+        extra = [float(x) for x in args.batch_taus.split(",") if x.strip()]
+        line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check, extra)
     if args.mcmc_chains > 0:
         line["mcmc"] = mcmc_leg(tor, args.mcmc_chains, args.mcmc_steps, args.mcmc_reps)
     if not args.no_cpu_baseline:
