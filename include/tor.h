@@ -230,7 +230,7 @@ double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches
  * synthetic instance (the work does not depend on the values) and makes the
  * fastest the default for that (n, tier) in this process. */
 
-/* best_bottom: host, the chosen s_b; ms: host, 5 doubles (s_b = 1..5, -1
+/* best_bottom: host, the chosen s_b; ms: host, 6 doubles (s_b = 1..6, -1
  * where not compiled for the tier), may be NULL.  Synchronous; 1 <= n <= TOR_NMAX. */
 int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, double* ms);
 /* Save / load the tuned table as text lines "n tier s_b". */

@@ -213,9 +213,9 @@ def results_of(cand) -> list:
 
 
 def tor_autotune(n: int, tier="dd", stream=None):
-    """(best s_b, times in ms for s_b = 1..5, -1 where not run)."""
+    """(best s_b, times in ms for s_b = 1..6, -1 where not run)."""
     best = ctypes.c_int32(0)
-    ms = np.zeros(5, dtype=np.float64)
+    ms = np.zeros(6, dtype=np.float64)
     check(lib().tor_autotune(int(n), tier_id(tier), _stream_ptr(stream), ctypes.byref(best),
                              ms.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tor_autotune")
     return int(best.value), ms

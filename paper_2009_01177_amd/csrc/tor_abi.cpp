@@ -1089,10 +1089,10 @@ int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, do
   double* dO = nullptr;
   TOR_HIP(hipMalloc((void**)&dO, sizeof(double) * h.size()));
   int rc = hip_err(hipMemcpy(dO, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
-  const int cand_max = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
+  const int cand_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 2);
   int best = 0;
   double best_ms = 1e300;
-  for (int sb = 1; sb <= 5; ++sb) {
+  for (int sb = 1; sb <= 6; ++sb) {
     if (ms) ms[sb - 1] = -1.0;
     if (rc != TOR_OK || sb > cand_max || sb > n) continue;
     tor_options_t o;
@@ -1152,7 +1152,7 @@ int tor_autotune_load(const char* path) {
   std::map<std::pair<int, int>, int> t;
   int a, b, c, rc = TOR_OK;
   while (fscanf(f, "%d %d %d", &a, &b, &c) == 3) {
-    if (a < 1 || a > TOR_NMAX || b < TOR_FP64 || b > TOR_QD || c < 1 || c > 5) rc = TOR_EINVAL;
+    if (a < 1 || a > TOR_NMAX || b < TOR_FP64 || b > TOR_QD || c < 1 || c > 6) rc = TOR_EINVAL;
     t[std::make_pair(a, b)] = c;
   }
   fclose(f);

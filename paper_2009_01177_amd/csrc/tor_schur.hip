@@ -563,26 +563,31 @@ struct Leaf {
   // is expanded: lane k holds entries k, k + 64, ... (indexes past the
   // matrix are clamped to its last entry and not stored).
   static constexpr int PF = (psize(SMEM::SM) + 63) / 64;
-  static_assert(PF <= 4, "prefetch holds at most four entries per lane");
+  static_assert(PF <= 6, "prefetch holds at most six entries per lane");
 
   __device__ __forceinline__ static void fetch(const R* mat, const R* gin, const int32_t* min_, int z,
-                                               int ps0, int lane, R& v0, R& v1, R& v2, R& v3, R& g,
+                                               int ps0, int lane, R& v0, R& v1, R& v2, R& v3, R& v4, R& v5, R& g,
                                                int32_t& m) {
     const R* src = mat + (size_t)z * ps0;
     v0 = src[min(lane, ps0 - 1)];
     if constexpr (PF > 1) v1 = src[min(lane + 64, ps0 - 1)];
     if constexpr (PF > 2) v2 = src[min(lane + 128, ps0 - 1)];
     if constexpr (PF > 3) v3 = src[min(lane + 192, ps0 - 1)];
+    if constexpr (PF > 4) v4 = src[min(lane + 256, ps0 - 1)];
+    if constexpr (PF > 5) v5 = src[min(lane + 320, ps0 - 1)];
     g = gin[z];
     m = min_[z];
   }
 
   __device__ __forceinline__ static void store(SMEM& sm, int ps0, int lane, const R& v0, const R& v1,
-                                               const R& v2, const R& v3, const R& g, int32_t m) {
+                                               const R& v2, const R& v3, const R& v4, const R& v5, const R& g,
+                                               int32_t m) {
     if (lane < ps0) sm.A[lane] = v0;
     if constexpr (PF > 1) if (lane + 64 < ps0) sm.A[lane + 64] = v1;
     if constexpr (PF > 2) if (lane + 128 < ps0) sm.A[lane + 128] = v2;
     if constexpr (PF > 3) if (lane + 192 < ps0) sm.A[lane + 192] = v3;
+    if constexpr (PF > 4) if (lane + 256 < ps0) sm.A[lane + 256] = v4;
+    if constexpr (PF > 5) if (lane + 320 < ps0) sm.A[lane + 320] = v5;
     if (lane == 0) {
       sm.gA[0] = g;
       sm.mA[0] = m;
@@ -695,7 +700,7 @@ struct Leaf {
     }
   }
 
-  // Expand state z (its matrix prefetched in v0..v3, g, m) through the
+  // Expand state z (its matrix prefetched in v0..v5, g, m) through the
   // middle levels; each lane then forms its own bottom state (leaf, lg,
   // lm) from its pair of the last middle level, in registers: both children
   // run the same code, the excluded one with zero pivot multipliers, whose
@@ -704,10 +709,10 @@ struct Leaf {
   // Then fetch the wave's next state zn.
   __device__ __forceinline__ static void expand(SMEM& sm, const R* mat, const R* gin, const int32_t* min_,
                                                 int zn, int nstates, int s_m, int L, int ps0, int lane,
-                                                bool& bad, R& v0, R& v1, R& v2, R& v3, R& g, int32_t& m,
+                                                bool& bad, R& v0, R& v1, R& v2, R& v3, R& v4, R& v5, R& g, int32_t& m,
                                                 R (&leaf)[psize(SB)], R& lg, int32_t& lm) {
-    store(sm, ps0, lane, v0, v1, v2, v3, g, m);
-    if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, g, m);
+    store(sm, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
+    if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
     wave_sync();
     R* cur;
     R* cg;
@@ -730,10 +735,10 @@ struct Leaf {
   __device__ __forceinline__ static void expand_pair(SMEM& sm, const R* mat, const R* gin,
                                                      const int32_t* min_, int zn, int nstates, int s_m,
                                                      int L, int ps0, int lane, bool& bad, R& v0, R& v1,
-                                                     R& v2, R& v3, R& g, int32_t& m, R (&P)[NP], R& pg,
+                                                     R& v2, R& v3, R& v4, R& v5, R& g, int32_t& m, R (&P)[NP], R& pg,
                                                      int32_t& pm) {
-    store(sm, ps0, lane, v0, v1, v2, v3, g, m);
-    if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, g, m);
+    store(sm, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
+    if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
     wave_sync();
     R* cur;
     R* cg;
@@ -810,7 +815,7 @@ struct Leaf {
 // a four-mode bottom), else one.
 template <class TT, int SB, int W>
 constexpr int leaf_waves_per_simd() {
-  return (W == 2 && !(TT::id == TOR_DD && SB >= 4)) ? 2 : 1;
+  return (W == 2 && !(TT::id == TOR_DD && SB >= 4) && !(TT::id == TOR_FP64 && SB >= 6)) ? 2 : 1;
 }
 
 // Whether the expanding wavefront hands its lanes' pair states over in
@@ -820,7 +825,7 @@ constexpr int leaf_waves_per_simd() {
 // four-mode bottom runs one wavefront per SIMD either way).
 template <class TT, int SB, int W>
 constexpr bool leaf_pair_in_registers() {
-  return W == 2 && TT::id == TOR_DD && SB >= 4;
+  return W == 2 && TT::id == TOR_DD && SB == 4;
 }
 
 template <class TT, int SB, int W>
@@ -850,13 +855,13 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
   const int zstride = W * (int)gridDim.x;
   bool bad = false;
   constexpr bool PR = leaf_pair_in_registers<TT, SB, W>();
-  R v0 = r_zero<R>(), v1 = v0, v2 = v0, v3 = v0, g = v0, lg = v0, pg = v0;
+  R v0 = r_zero<R>(), v1 = v0, v2 = v0, v3 = v0, v4 = v0, v5 = v0, g = v0, lg = v0, pg = v0;
   int32_t m = 0, lm = 0, pm = 0;
   R leaf[psize(SB)];
   R P[LF::NP];
 
   const int zb = W * (int)blockIdx.x;
-  if (zb + wv < nstates) LF::fetch(mat, gin, min_, zb + wv, ps0, lane, v0, v1, v2, v3, g, m);
+  if (zb + wv < nstates) LF::fetch(mat, gin, min_, zb + wv, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
   // W = 2: both wavefronts run the same loop, expand | barrier | bottom |
   // barrier, with wavefront 1 one barrier behind: barrier k of one pairs
   // with barrier k of the other, so each expansion starts after the other
@@ -868,10 +873,10 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
     const int z = zb + wv + t * zstride;
     if (z < nstates) {
       if constexpr (PR)
-        LF::expand_pair(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, g,
+        LF::expand_pair(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, v4, v5, g,
                         m, P, pg, pm);
       else
-        LF::expand(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, g, m,
+        LF::expand(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, v4, v5, g, m,
                    leaf, lg, lm);
     }
     if (W == 2) __syncthreads(); else wave_sync();
@@ -899,10 +904,11 @@ size_t schur_value_bytes(int tier) {
 }
 
 void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b) {
-  // bottom size by register budget (the defaults are the fastest measured
-  // at n = 12..30); six middle levels (64 bottom states)
-  const int sb_max = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
-  int sb = tier == TOR_FP64 ? 5 : (tier == TOR_DD ? 4 : 2);
+  // bottom size: the largest whose registers fit one wavefront per SIMD and
+  // whose middle levels leave two workgroups' LDS per CU (the fastest
+  // measured); six middle levels (64 bottom states)
+  const int sb_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 2);
+  int sb = sb_max;
   if (sb_req > 0) sb = sb_req < sb_max ? sb_req : sb_max;
   if (sb > n) sb = n;
   int sm = sb + 6;
@@ -1029,6 +1035,7 @@ static const void* leaf_fn() {
       case 3: return CALL(TierF64, 3);                            \
       case 4: return CALL(TierF64, 4);                            \
       case 5: return CALL(TierF64, 5);                            \
+      case 6: return CALL(TierF64, 6);                            \
       default: break;                                             \
     }                                                             \
   } else if (tier == TOR_DD) {                                    \
@@ -1037,6 +1044,7 @@ static const void* leaf_fn() {
       case 2: return CALL(TierDD, 2);                             \
       case 3: return CALL(TierDD, 3);                             \
       case 4: return CALL(TierDD, 4);                             \
+      case 5: return CALL(TierDD, 5);                             \
       default: break;                                             \
     }                                                             \
   } else {                                                        \
