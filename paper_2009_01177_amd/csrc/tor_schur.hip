@@ -821,11 +821,12 @@ constexpr int leaf_waves_per_simd() {
 // Whether the expanding wavefront hands its lanes' pair states over in
 // registers, so that the last middle level runs beside the bottom instead
 // of inside the expansion (which the other wavefront waits for): where the
-// registers allow it without lowering the occupancy (double-double with a
-// four-mode bottom runs one wavefront per SIMD either way).
+// registers allow it at one wavefront per SIMD (double-double with a
+// four-mode bottom, binary64 with a six-mode one; the five-mode
+// double-double pair state would need 312 more registers).
 template <class TT, int SB, int W>
 constexpr bool leaf_pair_in_registers() {
-  return W == 2 && TT::id == TOR_DD && SB == 4;
+  return W == 2 && ((TT::id == TOR_DD && SB == 4) || (TT::id == TOR_FP64 && SB == 6));
 }
 
 template <class TT, int SB, int W>
