@@ -811,8 +811,8 @@ struct Leaf {
 // (register arithmetic only).  Wavefront w takes states W * blockIdx.x + w + t * W *
 // gridDim.x, t = 0, 1, ...
 // Wavefronts per SIMD the register allocation aims at: two for the
-// two-wavefront kernel where its registers allow (all but double-double with
-// a four-mode bottom), else one.
+// two-wavefront kernel where its registers allow (not double-double with a
+// bottom of four or more modes, nor binary64 with six), else one.
 template <class TT, int SB, int W>
 constexpr int leaf_waves_per_simd() {
   return (W == 2 && !(TT::id == TOR_DD && SB >= 4) && !(TT::id == TOR_FP64 && SB >= 6)) ? 2 : 1;
