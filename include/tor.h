@@ -131,6 +131,33 @@ int tor_shutdown(void);
 int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_options_t* opt,
              void* stream, tor_result_t* out);
 
+/* A share of one Torontonian (Sec. 3.1, Eq. 2), for evaluations split over
+ * calls (checkpoint and resume: keep the finished parts' results) or over
+ * devices (the paper splits the 2^N subsets over its processes, Alg. 1).
+ * Part `part` of `nparts` covers the subsets Z whose decisions on the first
+ * k modes, k = ceil(log2 nparts), read as a binary number with mode 0 as its
+ * most significant bit (bit set = mode in Z), lie in
+ * [part 2^k / nparts, (part + 1) 2^k / nparts) (floor divisions): the parts
+ * are disjoint, cover every subset, and differ in size by at most a factor
+ * of two.  The definition does not depend on the tier or the options.
+ *   O, n, ld, tier, opt, stream   as tor_eval (opt->algo AUTO or SCHUR)
+ *   part, nparts   0 <= part < nparts; nparts <= 2^d where d is the depth at
+ *                  which the evaluation keeps its frontier (up to 10; fewer
+ *                  for small n), else TOR_EINVAL; n = 0 allows nparts = 1
+ *   out            host: tor = the part's signed sum, abs_sum its sum of
+ *                  magnitudes, err_bound and status as tor_eval
+ * Synchronous. */
+int tor_eval_part(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_options_t* opt,
+                  void* stream, int32_t part, int32_t nparts, tor_result_t* out);
+
+/* Tor from the results of all nparts parts of one instance (tor_eval_part,
+ * any order of evaluation), added in part order in the tier's arithmetic
+ * (double-double, quad-double for TOR_QD).  parts: host, nparts results, all
+ * with tier_used == tier; out: host.  status is the first part's non-OK
+ * status, if any.  Host only; no GPU needed. */
+int tor_combine_parts(int32_t tier, int32_t n, const tor_result_t* parts, int32_t nparts,
+                      tor_result_t* out);
+
 /* Torontonians of many instances of uneven n (the click patterns a sampler
  * scores, Sec. 7.1.1: about a hundred per sample), enqueued on `stream`.
  * Instances are grouped by (n, tier); each group's states are expanded

@@ -22,7 +22,7 @@ TOR_FLAG_GRAPH = 2
 # Every symbol include/tor.h declares.
 EXPORTS = (
     "tor_version", "tor_strerror", "tor_init", "tor_shutdown", "tor_eval", "tor_eval_batched",
-    "tor_mcmc",
+    "tor_mcmc", "tor_eval_part", "tor_combine_parts",
     "tor_debug_level_sums", "tor_debug_sampled_terms", "tor_last_kernel_ms",
     "tor_next_mask", "tor_kth_mask", "tor_plan_items",
     "tor_features", "tor_mlp_forward", "tor_mlp_grad", "tor_mlp_adam",
@@ -135,6 +135,11 @@ def lib():
     L.tor_eval_batched.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i32), i32,
                                    ctypes.POINTER(i32), ctypes.c_double, ctypes.POINTER(TorOptionsC),
                                    vp, vp]
+    L.tor_eval_part.restype = ctypes.c_int
+    L.tor_eval_part.argtypes = [vp, i32, i64, i32, ctypes.POINTER(TorOptionsC), vp, i32, i32,
+                                ctypes.POINTER(TorResultC)]
+    L.tor_combine_parts.restype = ctypes.c_int
+    L.tor_combine_parts.argtypes = [i32, i32, ctypes.POINTER(TorResultC), i32, ctypes.POINTER(TorResultC)]
     L.tor_mcmc.restype = ctypes.c_int
     L.tor_mcmc.argtypes = [vp, i32, i64, i32, i32, i32, vp, vp, i32, ctypes.c_double,
                            ctypes.POINTER(TorOptionsC), vp, vp, vp]

@@ -119,6 +119,34 @@ def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
     return _res(out)
 
 
+def tor_eval_part(O, part: int, nparts: int, tier="dd", stream=None, bottom_modes: int = 0,
+                  raise_on_error: bool = True) -> TorResult:
+    """Share `part` of `nparts` of Tor(O) (include/tor.h, tor_eval_part)."""
+    Od, n, ld = _device_o(O)
+    opt = _lib.TorOptionsC(_lib.TOR_ALGO_AUTO, -1, 0, 0, int(bottom_modes))
+    out = _lib.TorResultC()
+    rc = lib().tor_eval_part(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), ctypes.byref(opt),
+                             _stream_ptr(stream), int(part), int(nparts), ctypes.byref(out))
+    if rc != _lib.TOR_OK and raise_on_error:
+        raise TorError(rc, "tor_eval_part")
+    return _res(out)
+
+
+def tor_combine_parts(tier, n: int, parts) -> TorResult:
+    """Tor from the TorResults of all parts, in part order (host only)."""
+    arr = (_lib.TorResultC * max(len(parts), 1))()
+    for i, r in enumerate(parts):
+        arr[i].tor[:] = (list(r.expansion) + [0.0] * 4)[:4]
+        arr[i].abs_sum[:] = list(r.abs_sum)[:2]
+        arr[i].err_bound = r.err_bound
+        arr[i].tier_used = r.tier_used
+        arr[i].status = r.status
+    out = _lib.TorResultC()
+    check(lib().tor_combine_parts(tier_id(tier), int(n), arr, len(parts), ctypes.byref(out)),
+          "tor_combine_parts")
+    return _res(out)
+
+
 class Batch:
     """A packed batch on the device: instance k's O (2n_k x 2n_k, leading
     dimension 2n_k) at offsets[k] complex elements into one buffer."""

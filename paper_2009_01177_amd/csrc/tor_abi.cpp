@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "../../include/tor.h"
+#include "prec.hpp"
 #include "tor_host.h"
 #include "tor_internal.hpp"
 #include "tor_mcmc.hpp"
@@ -387,10 +388,16 @@ int fold(int tier, const void* part, int nseg, size_t seg_len, void* out, void* 
 
 // Enqueue a planned group.  O + offs_dev[k] (offs_dev NULL: O itself) is
 // instance k; results go to out[out_index ? out_index[k] : k] (device).
+// With one instance, only the depth-D_s states [z_lo, z_hi) are expanded and
+// summed (a share of the evaluation; the whole of it by default).
 int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const int64_t* offs_dev,
                         int64_t ld, const tor_options_t* opt, const int32_t* out_index,
-                        tor_result_t* out, bool timed, hipStream_t s) {
+                        tor_result_t* out, bool timed, hipStream_t s, size_t z_lo = 0,
+                        size_t z_hi = SIZE_MAX) {
   const int tier = p.tier, n = p.n;
+  const bool whole = z_lo == 0 && z_hi >= p.Ns;
+  if (!whole && (p.R != 1 || z_lo >= z_hi || z_hi > p.Ns)) return TOR_EINVAL;
+  if (whole) z_hi = p.Ns;
   char* B = w->buf;
   uint32_t* cnt = (uint32_t*)(B + p.o_cnt);
   int32_t* status = (int32_t*)(cnt + 1);
@@ -436,9 +443,8 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
     }
   }
   const size_t rb = p.rb, ab = p.ab;
-  for (int ch = 0; ch < p.nchunks; ++ch) {
-    const size_t first = (size_t)ch * p.Cr;
-    const int cr = (int)std::min<size_t>(p.Cr, p.Ns - first);
+  for (size_t first = z_lo; first < z_hi; first += p.Cr) {
+    const int cr = (int)std::min<size_t>(p.Cr, z_hi - first);
     const char* im = B + p.o_rm + rb * (first * psz(n - p.D_s));
     const char* ig = B + p.o_rg + rb * first;
     const int32_t* in_ = (const int32_t*)(B + p.o_rn) + first;
@@ -466,7 +472,10 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
     }
     TOR_TRY(fold(tier, B + p.o_part, cr, (size_t)1 << p.Dl, B + p.o_ds + ab * 2 * first, B + p.o_rsc, s));
   }
-  TOR_TRY(fold(tier, B + p.o_ds, p.R, (size_t)1 << p.D_s, B + p.o_inst, B + p.o_rsc, s));
+  if (whole)
+    TOR_TRY(fold(tier, B + p.o_ds, p.R, (size_t)1 << p.D_s, B + p.o_inst, B + p.o_rsc, s));
+  else
+    TOR_TRY(fold(tier, B + p.o_ds + ab * 2 * z_lo, 1, z_hi - z_lo, B + p.o_inst, B + p.o_rsc, s));
   const double err_rel = (double)(4 * n * n + n + 8) * unit_roundoff(tier);
   TOR_HIP(launch_finalize_batch(tier, B + p.o_inst, p.R, out_index, n, err_rel, out, s));
   w->last_d = p.D_m;
@@ -953,6 +962,72 @@ double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches
   if (grid) *grid = w->last_grid;
   if (launches) *launches = w->last_launches;
   return w->last_ms;
+}
+
+int tor_eval_part(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_options_t* opt,
+                  void* stream, int32_t part, int32_t nparts, tor_result_t* out) {
+  if (out == nullptr || nparts < 1 || part < 0 || part >= nparts) return TOR_EINVAL;
+  TOR_TRY(check_common(O, n, ld, tier));
+  if (opt && opt->algo != TOR_ALGO_AUTO && opt->algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
+  int k = 0;  // prefix modes that number the parts
+  while ((1 << k) < nparts) ++k;
+  if (n == 0) {
+    if (nparts != 1) return TOR_EINVAL;
+    fill_trivial(out, tier);
+    return TOR_OK;
+  }
+  SchurPlan p;
+  plan_schur(tier, n, 1, opt ? opt->bottom_modes : 0, &p);
+  if (k > p.D_s) return TOR_EINVAL;  // more parts than depth-D_s states
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  TOR_TRY(ensure_cap(w, p.bytes));
+  const size_t codes = (size_t)1 << k;
+  const size_t c_lo = (size_t)part * codes / (size_t)nparts;
+  const size_t c_hi = (size_t)(part + 1) * codes / (size_t)nparts;
+  const int sh = p.D_s - k;
+  const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
+  w->ev_pairs = 0;
+  tor_result_t* dres = (tor_result_t*)(w->buf + p.o_res);
+  TOR_TRY(enqueue_schur_group(w, p, O, nullptr, ld, opt, nullptr, dres, timed, s, c_lo << sh, c_hi << sh));
+  TOR_HIP(hipMemcpyAsync(w->host_res, dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
+  TOR_HIP(hipStreamSynchronize(s));
+  if (w->ev_pairs > 0) TOR_TRY(collect_ev(w));
+  *out = *w->host_res;
+  return out->status;
+}
+
+int tor_combine_parts(int32_t tier, int32_t n, const tor_result_t* parts, int32_t nparts,
+                      tor_result_t* out) {
+  if (!parts || !out || nparts < 1 || n < 0 || n > TOR_NMAX) return TOR_EINVAL;
+  if (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD) return TOR_EINVAL;
+  int status = TOR_OK;
+  prec::dd a{0.0, 0.0}, t2{0.0, 0.0};
+  prec::qd t4{{0.0, 0.0, 0.0, 0.0}};
+  for (int i = 0; i < nparts; ++i) {
+    const tor_result_t& r = parts[i];
+    if (r.tier_used != tier) return TOR_EINVAL;
+    if (r.status != TOR_OK && status == TOR_OK) status = r.status;
+    a = prec::dd_add(a, prec::dd{r.abs_sum[0], r.abs_sum[1]});
+    if (tier == TOR_QD)
+      t4 = prec::qd_add(t4, prec::qd{{r.tor[0], r.tor[1], r.tor[2], r.tor[3]}});
+    else
+      t2 = prec::dd_add(t2, prec::dd{r.tor[0], r.tor[1]});
+  }
+  memset(out, 0, sizeof(*out));
+  if (tier == TOR_QD) {
+    for (int i = 0; i < 4; ++i) out->tor[i] = t4.x[i];
+  } else {
+    out->tor[0] = t2.hi;
+    out->tor[1] = t2.lo;
+  }
+  out->abs_sum[0] = a.hi;
+  out->abs_sum[1] = a.lo;
+  out->err_bound = (double)(4 * n * n + n + 8) * unit_roundoff(tier) * a.hi;
+  out->tier_used = tier;
+  out->status = status;
+  return TOR_OK;
 }
 
 int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,

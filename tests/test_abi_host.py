@@ -123,3 +123,47 @@ def test_mcmc_argument_checks_need_no_gpu(L):
     assert call(P=None) == E                   # candidates needed when N > 0
     assert call(tier=5) == E
     assert call(tier=_lib.TOR_AUTO, tau=0.0) == E
+
+
+def test_combine_parts_needs_no_gpu(L):
+    from paper_2009_01177_amd import _lib
+    from fractions import Fraction as F
+    arr = (_lib.TorResultC * 3)()
+    vals = [(1.0, 2.0 ** -60), (2.0, -2.0 ** -58), (-0.5, 0.0)]
+    for i, (hi, lo) in enumerate(vals):
+        arr[i].tor[0], arr[i].tor[1] = hi, lo
+        arr[i].abs_sum[0] = abs(hi)
+        arr[i].tier_used = _lib.TOR_DD
+    out = _lib.TorResultC()
+    assert L.tor_combine_parts(_lib.TOR_DD, 10, arr, 3, ctypes.byref(out)) == 0
+    got = F(out.tor[0]) + F(out.tor[1])
+    assert got == sum(F(h) + F(l) for h, l in vals)
+    assert out.abs_sum[0] == 3.5 and out.status == 0 and out.tier_used == _lib.TOR_DD
+    # a part's failure is reported; a part of another tier is refused
+    arr[1].status = _lib.TOR_ENOTPD
+    assert L.tor_combine_parts(_lib.TOR_DD, 10, arr, 3, ctypes.byref(out)) == 0
+    assert out.status == _lib.TOR_ENOTPD
+    arr[2].tier_used = _lib.TOR_FP64
+    assert L.tor_combine_parts(_lib.TOR_DD, 10, arr, 3, ctypes.byref(out)) == _lib.TOR_EINVAL
+    assert L.tor_combine_parts(_lib.TOR_DD, 10, arr, 0, ctypes.byref(out)) == _lib.TOR_EINVAL
+    # quad-double parts keep all four words
+    q = (_lib.TorResultC * 2)()
+    for i in range(2):
+        q[i].tor[:] = [1.0, 2.0 ** -60, 2.0 ** -120, 2.0 ** -180]
+        q[i].tier_used = _lib.TOR_QD
+    assert L.tor_combine_parts(_lib.TOR_QD, 10, q, 2, ctypes.byref(out)) == 0
+    assert sum(F(x) for x in out.tor) == 2 * (1 + F(2) ** -60 + F(2) ** -120 + F(2) ** -180)
+
+
+def test_eval_part_argument_checks_need_no_gpu(L):
+    from paper_2009_01177_amd import _lib
+    out = _lib.TorResultC()
+    d = ctypes.c_void_p(16)
+    E = _lib.TOR_EINVAL
+    assert L.tor_eval_part(d, 10, 20, 1, None, None, 0, 0, ctypes.byref(out)) == E
+    assert L.tor_eval_part(d, 10, 20, 1, None, None, 3, 3, ctypes.byref(out)) == E
+    assert L.tor_eval_part(d, 10, 20, 1, None, None, -1, 3, ctypes.byref(out)) == E
+    assert L.tor_eval_part(d, 10, 20, 1, None, None, 0, 3, None) == E
+    assert L.tor_eval_part(None, 0, 0, 1, None, None, 0, 2, ctypes.byref(out)) == E
+    assert L.tor_eval_part(None, 0, 0, 1, None, None, 0, 1, ctypes.byref(out)) == 0
+    assert out.tor[0] == 1.0

@@ -1,0 +1,101 @@
+"""tor_eval_part / tor_combine_parts: every part's signed sum and sum of
+magnitudes against the binary128 oracle summed over exactly that part's
+subsets, and the combined parts against the oracle and against tor_eval.
+Parts are evaluated in any order (a resumed run)."""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import gbs_inputs as g
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "dd": 1e-25, "qd": 1e-30}
+
+
+@pytest.fixture(scope="module")
+def tor():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_01177_amd as t
+    t.tor_init()
+    return t
+
+
+_REF = {}
+
+
+def _reference(n, seed):
+    """Instance and the oracle's per-mask terms as exact Fractions."""
+    key = (n, seed)
+    if key not in _REF:
+        O = g.random_instance(n, seed)
+        masks = np.arange(1 << n, dtype=np.uint64)
+        d3, t3, st = oracle._terms3(O, masks)
+        assert (st == 0).all()
+        terms = [Fraction(t3[i, 0]) + Fraction(t3[i, 1]) + Fraction(t3[i, 2]) for i in range(1 << n)]
+        _REF[key] = (O, terms)
+    return _REF[key]
+
+
+def _part_of(mask, k, nparts):
+    code = 0
+    for i in range(k):
+        code = (code << 1) | ((mask >> i) & 1)
+    codes = 1 << k
+    for p in range(nparts):
+        if p * codes // nparts <= code < (p + 1) * codes // nparts:
+            return p
+    raise AssertionError
+
+
+@pytest.mark.parametrize("tier", ["fp64", "dd", "qd"])
+@pytest.mark.parametrize("nparts", [1, 2, 3, 5, 8])
+def test_parts_match_the_oracle(tor, tier, nparts):
+    n = 16
+    O, terms = _reference(n, 4242)
+    k = max(0, (nparts - 1).bit_length())
+    want = [Fraction(0)] * nparts
+    want_abs = [Fraction(0)] * nparts
+    for m, t in enumerate(terms):
+        p = _part_of(m, k, nparts)
+        want[p] += t
+        want_abs[p] += abs(t)
+    print(f"[parts] n={n} tier={tier} nparts={nparts}", flush=True)
+    res = []
+    for p in reversed(range(nparts)):  # any order
+        r = tor.tor_eval_part(O, p, nparts, tier=tier)
+        assert r.status == 0
+        assert float(abs(r.exact - want[p]) / want_abs[p]) <= TOL[tier], p
+        assert abs(r.abs_exact - want_abs[p]) <= 1e-12 * want_abs[p]
+        res.append(r)
+    res.reverse()
+    total = tor.tor_combine_parts(tier, n, res)
+    S = sum(want_abs)
+    assert float(abs(total.exact - sum(want)) / S) <= TOL[tier]
+    whole = tor.tor_eval(O, tier=tier, algo="schur")
+    assert float(abs(total.exact - whole.exact) / S) <= TOL[tier]
+    if nparts == 1:
+        assert total.exact == whole.exact
+
+
+def test_benchmark_instance_in_parts(tor):
+    # the n = 30 instance in 16 parts, evaluated last to first, against one
+    # whole evaluation
+    O, _ = g.workload("n30_lossy")
+    print("[parts] n=30 dd nparts=16", flush=True)
+    res = [tor.tor_eval_part(O, p, 16, tier="dd") for p in reversed(range(16))][::-1]
+    total = tor.tor_combine_parts("dd", 30, res)
+    whole = tor.tor_eval(O, tier="dd")
+    assert total.status == 0
+    assert float(abs(total.exact - whole.exact) / whole.abs_exact) <= 1e-25
+    assert abs(total.abs_exact - whole.abs_exact) <= 1e-25 * whole.abs_exact
+
+
+def test_too_many_parts_are_refused(tor):
+    O = g.random_instance(12, 7)
+    with pytest.raises(tor.TorError):
+        tor.tor_eval_part(O, 0, 4096, tier="dd")
