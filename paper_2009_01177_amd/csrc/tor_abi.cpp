@@ -1164,7 +1164,7 @@ int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, do
   double* dO = nullptr;
   TOR_HIP(hipMalloc((void**)&dO, sizeof(double) * h.size()));
   int rc = hip_err(hipMemcpy(dO, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
-  const int cand_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 2);
+  const int cand_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 3);
   int best = 0;
   double best_ms = 1e300;
   for (int sb = 1; sb <= 6; ++sb) {

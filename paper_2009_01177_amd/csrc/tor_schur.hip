@@ -811,11 +811,14 @@ struct Leaf {
 // (register arithmetic only).  Wavefront w takes states W * blockIdx.x + w + t * W *
 // gridDim.x, t = 0, 1, ...
 // Wavefronts per SIMD the register allocation aims at: two for the
-// two-wavefront kernel where its registers allow (not double-double with a
-// bottom of four or more modes, nor binary64 with six), else one.
+// two-wavefront kernel where its registers allow (not quad-double, not
+// double-double with a bottom of four or more modes, nor binary64 with six),
+// else one.
 template <class TT, int SB, int W>
 constexpr int leaf_waves_per_simd() {
-  return (W == 2 && !(TT::id == TOR_DD && SB >= 4) && !(TT::id == TOR_FP64 && SB >= 6)) ? 2 : 1;
+  return (W == 2 && TT::id != TOR_QD && !(TT::id == TOR_DD && SB >= 4) && !(TT::id == TOR_FP64 && SB >= 6))
+             ? 2
+             : 1;
 }
 
 // Whether the expanding wavefront hands its lanes' pair states over in
@@ -908,7 +911,7 @@ void schur_levels(int tier, int n, int sb_req, int* s_m, int* s_b) {
   // bottom size: the largest whose registers fit one wavefront per SIMD and
   // whose middle levels leave two workgroups' LDS per CU (the fastest
   // measured); six middle levels (64 bottom states)
-  const int sb_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 2);
+  const int sb_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 3);
   int sb = sb_max;
   if (sb_req > 0) sb = sb_req < sb_max ? sb_req : sb_max;
   if (sb > n) sb = n;
@@ -1001,12 +1004,12 @@ hipError_t launch_expand_multi(int tier, const void* in_mat, const void* in_g, c
   return hipGetLastError();
 }
 
-// Wavefronts per workgroup of the middle + bottom kernel: two where a
-// wavefront's registers fit twice in a SIMD (binary64 and double-double),
-// else one.
-template <class TT>
+// Wavefronts per workgroup of the middle + bottom kernel: two (taking turns
+// with the LDS), except quad-double with a bottom of one or two modes, whose
+// expansions outweigh its bottoms (measured slower with two).
+template <class TT, int SB>
 constexpr int leaf_waves() {
-  return TT::id == TOR_QD ? 1 : 2;
+  return (TT::id == TOR_QD && SB <= 2) ? 1 : 2;
 }
 
 template <class TT, int SB>
@@ -1014,7 +1017,7 @@ static hipError_t launch_leaf_t(const void* mat, const void* g, const int32_t* m
                                 int n, void* partials, int32_t* status, int grid, hipStream_t st) {
   using R = typename TT::R;
   using Acc = typename TT::Acc;
-  constexpr int W = leaf_waves<TT>();
+  constexpr int W = leaf_waves<TT, SB>();
   const int blocks = grid < (nst + W - 1) / W ? grid : (nst + W - 1) / W;
   hipLaunchKernelGGL((leaf_kernel<TT, SB, W>), dim3(blocks), dim3(64 * W), 0, st, (const R*)mat,
                      (const R*)g, m, s_m, nst, n, (Acc*)partials, status);
@@ -1023,7 +1026,7 @@ static hipError_t launch_leaf_t(const void* mat, const void* g, const int32_t* m
 
 template <class TT, int SB>
 static const void* leaf_fn() {
-  return reinterpret_cast<const void*>(&leaf_kernel<TT, SB, leaf_waves<TT>()>);
+  return reinterpret_cast<const void*>(&leaf_kernel<TT, SB, leaf_waves<TT, SB>()>);
 }
 
 // Compiled (tier, s_b) combinations: s_b is the tier's register budget, or n
@@ -1052,6 +1055,7 @@ static const void* leaf_fn() {
     switch (s_b) {                                                \
       case 1: return CALL(TierQD, 1);                             \
       case 2: return CALL(TierQD, 2);                             \
+      case 3: return CALL(TierQD, 3);                             \
       default: break;                                             \
     }                                                             \
   }                                                               \
@@ -1067,7 +1071,7 @@ hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* 
 
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu) {
 #define CALL(TT, SBV) \
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, leaf_fn<TT, SBV>(), 64 * leaf_waves<TT>(), 0)
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, leaf_fn<TT, SBV>(), 64 * leaf_waves<TT, SBV>(), 0)
   TOR_LEAF_DISPATCH(CALL)
 #undef CALL
 }

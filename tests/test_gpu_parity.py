@@ -311,7 +311,7 @@ def test_library_before_torch_keeps_torch_on_the_gpu(tor):
 # middle states), one to three workgroups: the two-wavefront alternation with
 # short and uneven rounds
 @pytest.mark.parametrize("tier,sb", [("fp64", s) for s in range(1, 7)] + [("dd", s) for s in range(1, 6)]
-                         + [("qd", s) for s in range(1, 3)])
+                         + [("qd", s) for s in range(1, 4)])
 @pytest.mark.parametrize("extra", [1, 3])
 def test_every_bottom_size_and_small_grids(tor, tier, sb, extra):
     n = sb + 6 + extra
