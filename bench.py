@@ -294,6 +294,49 @@ def mcmc_leg(tor, chains: int, steps: int, reps: int):
     return out
 
 
+def stress_leg(tor, taus=(1e-3, 1e-6)):
+    """Precision-stress workload: n = 36 of a 100-mode state with r = 1.5 and
+    transmission 0.5, in FP64, DD and QD (QD as the reference), and what the
+    precision selector picks and costs for it at each accuracy target."""
+    import torch
+    import gbs_inputs as g
+    from paper_2009_01177_amd import selector
+    selector.load_default()
+    O, _ = g.workload("n36_stress")
+    Od = torch.from_numpy(O).to("cuda:0")
+    out = {"workload": "single Torontonian n=36: 100-mode GBS (Haar U, r=1.5, eta=0.5), 36 clicked "
+                       "modes, O 72x72 complex128"}
+    res = {}
+    for tier in ("fp64", "dd", "qd"):
+        if tier != "qd":
+            tor.tor_eval(Od, tier=tier)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res[tier] = tor.tor_eval(Od, tier=tier)
+        torch.cuda.synchronize()
+        out[tier] = {"s": time.perf_counter() - t}
+        print(f"[bench] n=36 {tier}: {out[tier]['s']:.3f} s", file=sys.stderr, flush=True)
+    q = res["qd"]
+    out["kappa"] = q.kappa
+    for tier in ("fp64", "dd"):
+        out[tier]["rel_err_vs_qd"] = float(abs(res[tier].exact - q.exact) / abs(q.exact))
+        out[tier]["err_vs_qd_over_sabs"] = float(abs(res[tier].exact - q.exact) / q.abs_exact)
+    b = tor.Batch([O])
+    out["selector"] = {}
+    for tau in taus:
+        tiers, k, src = tor.tor_select_tiers(b, tau)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = tor.tor_eval_batched(b, tau=tau)[0]
+        sec = time.perf_counter() - t
+        out["selector"][repr(tau)] = {
+            "tier": ["fp64", "dd", "qd"][int(tiers[0])], "log10_kappa_pred": float(k[0]),
+            "source": "network" if int(src[0]) == 0 else "bound estimate", "s": sec,
+            "rel_err_vs_qd": float(abs(r.exact - q.exact) / abs(q.exact))}
+        print(f"[bench] n=36 tau={tau:g}: {out['selector'][repr(tau)]}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +360,8 @@ def main():
     ap.add_argument("--mcmc-chains", type=int, default=1024, help="sampler leg chains (0: skip)")
     ap.add_argument("--mcmc-steps", type=int, default=16)
     ap.add_argument("--mcmc-reps", type=int, default=2)
+    ap.add_argument("--stress", action="store_true",
+                    help="also run the n = 36 precision-stress leg (about a minute: QD reference)")
     ap.add_argument("--mcmc-only", action="store_true",
                     help="run only the sampler leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -413,6 +458,8 @@ def main():
         line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check, extra)
     if args.mcmc_chains > 0:
         line["mcmc"] = mcmc_leg(tor, args.mcmc_chains, args.mcmc_steps, args.mcmc_reps)
+    if args.stress:
+        line["stress_n36"] = stress_leg(tor)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(O, n, args.cpu_seconds)

@@ -3,9 +3,11 @@
 The selector predicts y = log10(S_abs / |Tor|), the cancellation ratio that
 decides how many of a tier's bits survive the alternating sum (Sec. 5.1),
 from the 12 features of tor_features.  Labels come from the library's own
-quad-double evaluations; the per-tier error model
-|dTor|/|Tor| <= C_t kappa^s_t u_t is calibrated from FP64 and double-double
-evaluations of the same instances.  Forward passes, gradients and Adam steps
+quad-double evaluations, and for larger n (where quad-double is slow) from
+double-double ones, which resolve kappa far below their 1e25 or so; the
+per-tier error model |dTor|/|Tor| <= C_t kappa^s_t u_t is calibrated from
+FP64 and double-double evaluations of the same instances (FP64 against the
+reference tier; double-double only where quad-double is the reference).  Forward passes, gradients and Adam steps
 run in the library's HIP kernels (tor_mlp_forward / tor_mlp_grad /
 tor_mlp_adam); this module only drives them.
 """
@@ -52,29 +54,35 @@ def training_instances(count: int, nlo: int, nhi: int, seed: int, M: int = 60):
 @dataclass
 class Labels:
     X: np.ndarray        # (B, 12) features
-    y: np.ndarray        # log10 kappa from the QD tier
-    err: dict            # tier -> relative forward error |T_t - T_qd| / |T_qd|
+    y: np.ndarray        # log10 kappa from the reference tier
+    err: dict            # tier -> relative forward error |T_t - T_ref| / |T_ref| (nan: no reference)
     n: np.ndarray
 
+    def __add__(self, o: "Labels") -> "Labels":
+        return Labels(np.concatenate([self.X, o.X]), np.concatenate([self.y, o.y]),
+                      {t: np.concatenate([self.err[t], o.err[t]]) for t in self.err},
+                      np.concatenate([self.n, o.n]))
 
-def label(Os, chunk: int = 1024) -> Labels:
-    """Features and labels of instances, all on the GPU."""
+
+def label(Os, chunk: int = 1024, ref: str = "qd") -> Labels:
+    """Features and labels of instances, all on the GPU.  ref: the tier whose
+    value and S_abs give kappa, "qd" or (for large n) "dd"."""
     Xs, ys, e0, e1, ns = [], [], [], [], []
     for i in range(0, len(Os), chunk):
         part = Os[i:i + chunk]
         b = Batch(part)
         X = tor_features(b).cpu().numpy()
-        rq = tor_eval_batched(b, tiers="qd")
+        rr = tor_eval_batched(b, tiers=ref)
         r0 = tor_eval_batched(b, tiers="fp64")
-        r1 = tor_eval_batched(b, tiers="dd")
+        r1 = tor_eval_batched(b, tiers="dd") if ref == "qd" else None
         for k in range(len(part)):
-            tq = rq[k].exact
-            sa = rq[k].abs_exact
+            tq = rr[k].exact
+            sa = rr[k].abs_exact
             y = float(math.log10(sa / abs(tq))) if tq != 0 else YMAX
             ys.append(min(y, YMAX))
             den = abs(tq) if tq != 0 else sa
             e0.append(float(abs(r0[k].exact - tq) / den))
-            e1.append(float(abs(r1[k].exact - tq) / den))
+            e1.append(float(abs(r1[k].exact - tq) / den) if r1 is not None else float("nan"))
         Xs.append(X)
         ns.append(b.n.copy())
     return Labels(np.concatenate(Xs), np.array(ys), {0: np.array(e0), 1: np.array(e1)},
@@ -146,7 +154,7 @@ def calibrate(lab: Labels, slack: float = 0.3):
     cs, ss = [], []
     for t in (0, 1):
         e = lab.err[t]
-        ok = e > 0
+        ok = np.isfinite(e) & (e > 0)
         if not ok.any():
             cs.append(0.0)
             ss.append(1.0)
@@ -186,10 +194,13 @@ def make_selector(theta, mean, std, lab: Labels, log10_c, slopes=(1.0, 1.0, 1.0)
 
 
 def fit_and_install(count: int = 3000, nlo: int = 6, nhi: int = 24, seed: int = 7, epochs: int = 300,
-                    path: str | None = None, verbose: bool = False):
-    """Generate, label, train, calibrate; install the selector (and save it)."""
+                    path: str | None = None, verbose: bool = False, count_dd: int = 0, nhi_dd: int = 0):
+    """Generate, label, train, calibrate; install the selector (and save it).
+    count_dd instances with n in (nhi, nhi_dd] are labelled by the DD tier."""
     Os = training_instances(count, nlo, nhi, seed)
     lab = label(Os)
+    if count_dd > 0 and nhi_dd > nhi:
+        lab = lab + label(training_instances(count_dd, nhi + 1, nhi_dd, seed + 1), chunk=64, ref="dd")
     theta, mean, std, losses = train(lab.X, lab.y, epochs=epochs, seed=seed,
                                      log_every=50 if verbose else 0)
     log10_c, slopes = calibrate(lab)
@@ -225,6 +236,9 @@ if __name__ == "__main__":
     ap.add_argument("--nhi", type=int, default=26)
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--seed", type=int, default=11)
+    ap.add_argument("--count-dd", type=int, default=0,
+                    help="further instances with n in (nhi, nhi-dd], labelled by the DD tier")
+    ap.add_argument("--nhi-dd", type=int, default=0)
     ap.add_argument("--out", default=DEFAULT_PATH)
     a = ap.parse_args()
     if not a.train:
@@ -234,6 +248,10 @@ if __name__ == "__main__":
     Os = training_instances(a.count, a.nlo, a.nhi, a.seed)
     print(f"[selector] {len(Os)} instances, n {a.nlo}..{a.nhi}", flush=True)
     lab = label(Os)
+    if a.count_dd > 0 and a.nhi_dd > a.nhi:
+        Od = training_instances(a.count_dd, a.nhi + 1, a.nhi_dd, a.seed + 1)
+        print(f"[selector] {len(Od)} instances, n {a.nhi + 1}..{a.nhi_dd} (DD reference)", flush=True)
+        lab = lab + label(Od, chunk=64, ref="dd")
     print(f"[selector] labelled in {time.time() - t0:.1f} s; log10 kappa "
           f"{lab.y.min():.2f}..{lab.y.max():.2f}", flush=True)
     theta, mean, std, losses = train(lab.X, lab.y, epochs=a.epochs, seed=a.seed, log_every=50)
