@@ -970,7 +970,7 @@ int tor_eval_part(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_
   TOR_TRY(check_common(O, n, ld, tier));
   if (opt && opt->algo != TOR_ALGO_AUTO && opt->algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
   int k = 0;  // prefix modes that number the parts
-  while ((1 << k) < nparts) ++k;
+  while (((int64_t)1 << k) < (int64_t)nparts) ++k;
   if (n == 0) {
     if (nparts != 1) return TOR_EINVAL;
     fill_trivial(out, tier);

@@ -164,6 +164,7 @@ def test_eval_part_argument_checks_need_no_gpu(L):
     assert L.tor_eval_part(d, 10, 20, 1, None, None, 3, 3, ctypes.byref(out)) == E
     assert L.tor_eval_part(d, 10, 20, 1, None, None, -1, 3, ctypes.byref(out)) == E
     assert L.tor_eval_part(d, 10, 20, 1, None, None, 0, 3, None) == E
+    assert L.tor_eval_part(d, 12, 24, 1, None, None, 0, 2 ** 31 - 1, ctypes.byref(out)) == E
     assert L.tor_eval_part(None, 0, 0, 1, None, None, 0, 2, ctypes.byref(out)) == E
     assert L.tor_eval_part(None, 0, 0, 1, None, None, 0, 1, ctypes.byref(out)) == 0
     assert out.tor[0] == 1.0
