@@ -294,6 +294,29 @@ def mcmc_leg(tor, chains: int, steps: int, reps: int):
     return out
 
 
+def small_leg(tor, reps: int = 20):
+    """The 16-mode lossless instance (65,536 subsets; launch-latency bound):
+    ms per evaluation in FP64 and DD, and the binary128 oracle's full
+    evaluation on the host beside it, with both errors over S_abs."""
+    import torch
+    import gbs_inputs as g
+    import oracle
+    O, _ = g.workload("n16_lossless")
+    Od = torch.from_numpy(O).to("cuda:0")
+    out = {"workload": "single Torontonian n=16: 16-mode lossless GBS (Haar U, r~U[0.5,1.0]), "
+                       "all modes clicked, O 32x32 complex128"}
+    t = time.perf_counter()
+    ref = oracle.tor(O)
+    out["oracle_s"] = time.perf_counter() - t
+    out["oracle_threads"] = ref["threads"]
+    for tier in ("fp64", "dd"):
+        ms, _, res = time_tier(tor, Od, tier, reps, 2)
+        out[tier] = {"ms": ms, "err_over_sabs": float(abs(res.exact - ref["tor"]) / ref["abs_sum"])}
+    print(f"[bench] n=16: fp64 {out['fp64']['ms']:.3f} ms, dd {out['dd']['ms']:.3f} ms, oracle "
+          f"{out['oracle_s']:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
 def stress_leg(tor, taus=(1e-3, 1e-6)):
     """Precision-stress workload: n = 36 of a 100-mode state with r = 1.5 and
     transmission 0.5, in FP64, DD and QD (QD as the reference), and what the
@@ -360,6 +383,7 @@ def main():
     ap.add_argument("--mcmc-chains", type=int, default=1024, help="sampler leg chains (0: skip)")
     ap.add_argument("--mcmc-steps", type=int, default=16)
     ap.add_argument("--mcmc-reps", type=int, default=2)
+    ap.add_argument("--no-small", action="store_true", help="skip the n = 16 leg")
     ap.add_argument("--stress", action="store_true",
                     help="also run the n = 36 precision-stress leg (about a minute: QD reference)")
     ap.add_argument("--mcmc-only", action="store_true",
@@ -458,6 +482,8 @@ def main():
         line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check, extra)
     if args.mcmc_chains > 0:
         line["mcmc"] = mcmc_leg(tor, args.mcmc_chains, args.mcmc_steps, args.mcmc_reps)
+    if not args.no_small:
+        line["small_n16"] = small_leg(tor)
     if args.stress:
         line["stress_n36"] = stress_leg(tor)
     if not args.no_cpu_baseline:
