@@ -99,3 +99,18 @@ def test_too_many_parts_are_refused(tor):
     O = g.random_instance(12, 7)
     with pytest.raises(tor.TorError):
         tor.tor_eval_part(O, 0, 4096, tier="dd")
+
+
+def test_interrupted_run_resumes_from_its_checkpoint(tor, tmp_path):
+    from paper_2009_01177_amd import parts
+    O = g.random_instance(22, 99)
+    ck = str(tmp_path / "run.json")
+    print("[parts] n=22 dd: 3 of 8 parts, then resume", flush=True)
+    assert parts.evaluate_in_parts(O, 8, "dd", checkpoint=ck, stop_after=3) is None
+    seen = []
+    total = parts.evaluate_in_parts(O, 8, "dd", checkpoint=ck, progress=lambda p, r: seen.append(p))
+    assert seen == [3, 4, 5, 6, 7]
+    straight = parts.evaluate_in_parts(O, 8, "dd")
+    assert total.exact == straight.exact
+    whole = tor.tor_eval(O, tier="dd")
+    assert float(abs(total.exact - whole.exact) / whole.abs_exact) <= 1e-25
