@@ -57,13 +57,13 @@ __device__ __forceinline__ dd r_fms2(dd t, dd a, dd b, dd c, dd d) { return prec
 
 __device__ __forceinline__ qd r_add(qd a, qd b) { return prec::qd_add(a, b); }
 __device__ __forceinline__ qd r_sub(qd a, qd b) { return prec::qd_sub(a, b); }
-__device__ __forceinline__ qd r_mul(qd a, qd b) { return prec::qd_mul(a, b); }
+__device__ __forceinline__ qd r_mul(qd a, qd b) { return prec::qd_mul_fast(a, b); }
 __device__ __forceinline__ qd r_neg(qd a) { return prec::qd_neg(a); }
 __device__ __forceinline__ double r_lead(qd a) { return a.x[0]; }
 __device__ __forceinline__ qd r_rsqrt(qd a) { return prec::qd_rsqrt(a); }
-__device__ __forceinline__ qd r_fms(qd c, qd a, qd b) { return prec::qd_sub(c, prec::qd_mul(a, b)); }
-__device__ __forceinline__ qd r_fma(qd c, qd a, qd b) { return prec::qd_add(c, prec::qd_mul(a, b)); }
-__device__ __forceinline__ qd r_fms2(qd t, qd a, qd b, qd c, qd d) { return r_fms(r_fms(t, a, b), c, d); }
+__device__ __forceinline__ qd r_fms(qd c, qd a, qd b) { return prec::qd_fms(c, a, b); }
+__device__ __forceinline__ qd r_fma(qd c, qd a, qd b) { return prec::qd_fms(c, prec::qd_neg(a), b); }
+__device__ __forceinline__ qd r_fms2(qd t, qd a, qd b, qd c, qd d) { return prec::qd_fms2(t, a, b, c, d); }
 
 template <class R>
 __device__ __forceinline__ R r_zero();

@@ -102,3 +102,72 @@ def test_composed_operations_meet_their_published_bounds(cases):
         tc = _val(t) + _val(c)
         if tc != 0:
             assert abs(_val(s) - tc) <= (3 * U * U + 13 * U ** 3) * abs(tc)
+
+
+QD_HARNESS = r"""
+#include "prec.hpp"
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+using namespace prec;
+static std::mt19937_64 g;
+static std::uniform_real_distribution<double> U(-1.0, 1.0);
+qd mk() {
+  double t[4];
+  t[0] = ldexp(U(g), (int)(U(g) * 8));
+  t[1] = U(g) * 0x1p-53 * t[0];
+  t[2] = U(g) * 0x1p-106 * t[0];
+  t[3] = U(g) * 0x1p-159 * t[0];
+  return qd_compress<4>(t);
+}
+void pr(qd a) { printf(" %a %a %a %a", a.x[0], a.x[1], a.x[2], a.x[3]); }
+int main(int argc, char** argv) {
+  g.seed(atoi(argv[1]));
+  const int count = atoi(argv[2]);
+  for (int i = 0; i < count; ++i) {
+    const int mode = i % 4;
+    qd a = mk(), b = mk(), c = mk(), d = mk(), t = mk();
+    if (mode == 1) t = qd_add(qd_mul(a, b), qd_mul(c, d));  // near-total cancellation
+    if (mode == 2) t = qd_mul(a, b);                          // t - ab ~ 0
+    if (mode == 3) { c = a; d = b; }
+    pr(t); pr(a); pr(b); pr(c); pr(d);
+    pr(qd_mul_fast(a, b)); pr(qd_fms(t, a, b)); pr(qd_fms2(t, a, b, c, d));
+    printf("\n");
+  }
+  return 0;
+}
+"""
+
+U4 = F(1, 2 ** 212)
+
+
+@pytest.fixture(scope="module")
+def qd_cases(tmp_path_factory):
+    d = tmp_path_factory.mktemp("qdprec")
+    src, exe = d / "q.cpp", d / "q"
+    src.write_text(QD_HARNESS)
+    r = subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-I",
+                        os.path.join(ROOT, "paper_2009_01177_amd", "csrc"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe), "11", "2000"], capture_output=True, text=True, check=True).stdout
+    rows = []
+    for line in out.splitlines():
+        v = [F(float.fromhex(x)) for x in line.split()]
+        rows.append([sum(v[4 * k:4 * k + 4]) for k in range(8)])
+    return rows
+
+
+def test_quad_double_fused_operations_within_their_bounds(qd_cases):
+    # product, t - ab and t - ab - cd from one compression each: within
+    # 4 u^4 of the magnitudes (1.0 to 1.3 u^4 measured)
+    worst = [F(0)] * 3
+    for t, a, b, c, d, m, f1, f2 in qd_cases:
+        ab, cd = a * b, c * d
+        for k, (val, ref, mag) in enumerate(((m, ab, abs(ab)), (f1, t - ab, abs(t) + abs(ab)),
+                                              (f2, t - ab - cd, abs(t) + abs(ab) + abs(cd)))):
+            if mag:
+                err = abs(val - ref)
+                assert err <= 4 * U4 * mag, (k, float(err / (U4 * mag)))
+                worst[k] = max(worst[k], err / (U4 * mag))
+    assert all(w > 0 for w in worst)  # the cases do exercise rounding
