@@ -410,12 +410,24 @@ PREC_HD qd qd_recip(qd y) {
 
 PREC_HD qd qd_div(qd x, qd y) { return qd_mul(x, qd_recip(y)); }
 
-// 1/sqrt(x) by Newton from double-double: y <- y + y (1 - x y^2) / 2.
+// 1/sqrt(x) by one Newton step from double-double, y <- y + y (1 - x y^2) / 2:
+// y0 has two words, so y0^2 is exact as six terms (TwoProds of the words);
+// x y0^2 is one quad-double product; h = 1 - x y0^2 is of order u^2 and
+// accurate to about u^4, so the correction y0 h / 2 needs only a
+// double-double product.
 PREC_HD qd qd_rsqrt(qd x) {
-  dd y0 = dd_rsqrt(dd{x.x[0], x.x[1]});
-  qd y = qd_from_dd(y0);
-  qd h = qd_add_d(qd_neg(qd_mul(x, qd_mul(y, y))), 1.0);
-  return qd_add(y, qd_mul_d(qd_mul(y, h), 0.5));
+  const dd y0 = dd_rsqrt(dd{x.x[0], x.x[1]});
+  double t[6];
+  two_prod(y0.hi, y0.hi, t[0], t[2]);
+  two_prod(2.0 * y0.hi, y0.lo, t[1], t[3]);
+  two_prod(y0.lo, y0.lo, t[4], t[5]);
+  const qd y2 = qd_compress<6>(t);
+  const qd h = qd_add_d(qd_neg(qd_mul_fast(x, y2)), 1.0);
+  // h's words need not be normalised after that cancellation (its first
+  // word is often exactly 0): add them up as a double-double
+  const dd hd = dd_add_d(dd_add_d(dd_add_d(dd{h.x[0], 0.0}, h.x[1]), h.x[2]), h.x[3]);
+  const dd c = dd_mul(y0, hd);
+  return qd_add_dd(qd_from_dd(y0), dd{0.5 * c.hi, 0.5 * c.lo});
 }
 
 // sqrt(x) = x * rsqrt(x), then one Newton correction s + (x - s^2)/(2s).

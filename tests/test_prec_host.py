@@ -132,6 +132,8 @@ int main(int argc, char** argv) {
     if (mode == 3) { c = a; d = b; }
     pr(t); pr(a); pr(b); pr(c); pr(d);
     pr(qd_mul_fast(a, b)); pr(qd_fms(t, a, b)); pr(qd_fms2(t, a, b, c, d));
+    qd x = a.x[0] < 0.0 ? qd_neg(a) : a;
+    pr(x); pr(qd_rsqrt(x));
     printf("\n");
   }
   return 0;
@@ -154,7 +156,7 @@ def qd_cases(tmp_path_factory):
     rows = []
     for line in out.splitlines():
         v = [F(float.fromhex(x)) for x in line.split()]
-        rows.append([sum(v[4 * k:4 * k + 4]) for k in range(8)])
+        rows.append([sum(v[4 * k:4 * k + 4]) for k in range(10)])
     return rows
 
 
@@ -162,7 +164,7 @@ def test_quad_double_fused_operations_within_their_bounds(qd_cases):
     # product, t - ab and t - ab - cd from one compression each: within
     # 4 u^4 of the magnitudes (1.0 to 1.3 u^4 measured)
     worst = [F(0)] * 3
-    for t, a, b, c, d, m, f1, f2 in qd_cases:
+    for t, a, b, c, d, m, f1, f2, x, r in qd_cases:
         ab, cd = a * b, c * d
         for k, (val, ref, mag) in enumerate(((m, ab, abs(ab)), (f1, t - ab, abs(t) + abs(ab)),
                                               (f2, t - ab - cd, abs(t) + abs(ab) + abs(cd)))):
@@ -171,3 +173,19 @@ def test_quad_double_fused_operations_within_their_bounds(qd_cases):
                 assert err <= 4 * U4 * mag, (k, float(err / (U4 * mag)))
                 worst[k] = max(worst[k], err / (U4 * mag))
     assert all(w > 0 for w in worst)  # the cases do exercise rounding
+
+
+def test_quad_double_rsqrt_within_its_bound(qd_cases):
+    # one Newton step from the double-double estimate (about 7 u^2): the
+    # quadratic term 1.5 (7 u^2)^2 dominates; 128 u^4 relative is the pin
+    import mpmath
+    mpmath.mp.prec = 400
+    u4 = mpmath.mpf(2) ** -212
+    worst = mpmath.mpf(0)
+    for *_, x, r in qd_cases:
+        ref = 1 / mpmath.sqrt(mpmath.mpf(x.numerator) / x.denominator)
+        got = mpmath.mpf(r.numerator) / r.denominator
+        rel = abs(got - ref) / (u4 * ref)
+        assert rel <= 128, float(rel)
+        worst = max(worst, rel)
+    assert worst > 0
