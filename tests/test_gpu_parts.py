@@ -114,3 +114,29 @@ def test_interrupted_run_resumes_from_its_checkpoint(tor, tmp_path):
     assert total.exact == straight.exact
     whole = tor.tor_eval(O, tier="dd")
     assert float(abs(total.exact - whole.exact) / whole.abs_exact) <= 1e-25
+
+
+def test_a_share_of_the_benchmark_instance_against_the_oracle(tor):
+    # the n = 30 benchmark instance through the timed kernels (the default
+    # bottom sizes and launch shape): the share of 1024 whose decisions on
+    # modes 0..9 are "in, out x8, in" (2^20 subsets), against the binary128
+    # oracle's terms for exactly those subsets
+    import math
+    O, _ = g.workload("n30_lossy")
+    nparts, k = 1024, 10
+    code = 0b1000000001
+    pre = 0
+    for i in range(k):
+        if (code >> (k - 1 - i)) & 1:
+            pre |= 1 << i
+    masks = np.uint64(pre) | (np.arange(1 << 20, dtype=np.uint64) << np.uint64(k))
+    print("[parts] n=30 share 513 of 1024: oracle terms for 2^20 subsets", flush=True)
+    d3, t3, st = oracle._terms3(O, masks)
+    assert (st == 0).all()
+    want = sum(map(Fraction, t3.ravel()))
+    sabs = math.fsum(np.abs(t3[:, 0]))
+    for tier in ("dd", "fp64"):
+        r = tor.tor_eval_part(O, code, nparts, tier=tier)
+        assert r.status == 0
+        assert float(abs(r.exact - want)) <= TOL[tier] * sabs, tier
+        assert abs(float(r.abs_exact) - sabs) <= 1e-12 * sabs
