@@ -84,3 +84,30 @@ def test_config3_like_batch(tor):
     for O, r in zip(Os, res):
         ref = oracle.tor(O)
         assert float(abs(r.exact - ref["tor"]) / ref["abs_sum"]) <= 1e-25
+
+
+def test_the_full_benchmark_batch_sampled(tor):
+    """The whole 4096-pattern batch (n ~ U{8..24}) in one graph-captured
+    launch sequence, as bench.py times it, in fixed DD and with selected
+    tiers at tau = 1e-3: 40 instances with n <= 14 against the binary128
+    oracle, 8 with n >= 22 against their single quad-double evaluation."""
+    from paper_2009_01177_amd import selector
+    Os = g.batched_workload(batch=4096)
+    ns = np.array([O.shape[0] // 2 for O in Os])
+    b = tor.Batch(Os)
+    print("[batched] full 4096 batch, dd and auto", flush=True)
+    dd = tor.tor_eval_batched(b, tiers="dd", graph=True)
+    selector.load_default()
+    auto = tor.tor_eval_batched(b, tau=1e-3, graph=True)
+    small = np.flatnonzero(ns <= 14)[:40]
+    large = np.flatnonzero(ns >= 22)[:8]
+    assert len(small) == 40 and len(large) == 8
+    for k in small:
+        ref = oracle.tor(Os[k])
+        assert float(abs(dd[k].exact - ref["tor"]) / ref["abs_sum"]) <= 1e-25, k
+        if ref["tor"] != 0:
+            assert float(abs(auto[k].exact - ref["tor"]) / abs(ref["tor"])) <= 1e-3, k
+    for k in large:
+        q = tor.tor_eval(Os[k], tier="qd")
+        assert float(abs(dd[k].exact - q.exact) / q.abs_exact) <= 1e-25, k
+        assert float(abs(auto[k].exact - q.exact) / abs(q.exact)) <= 1e-3, k
