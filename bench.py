@@ -221,6 +221,7 @@ def batched_leg(tor, count: int, tau: float, steps: int, check: bool, extra_taus
     out["auto_learned"] = {"s": s_ml, "solves_per_s": count / s_ml, "stats": st_ml,
                            "selector": "paper_2009_01177_amd/data/selector_default.txt" if have else None}
     out["gain_learned_vs_fixed_dd"] = s_dd / s_ml
+    out["select_ms"] = timed(lambda: tor.tor_select_tiers(b, tau), steps) * 1e3
     out["gain_learned_vs_bounds_only"] = s_fb / s_ml
     print(f"[bench] batched auto: bounds-only {s_fb * 1e3:.1f} ms, learned {s_ml * 1e3:.1f} ms "
           f"({st_ml})", file=sys.stderr, flush=True)
@@ -237,6 +238,18 @@ def batched_leg(tor, count: int, tau: float, steps: int, check: bool, extra_taus
                 worst = max(worst, float(abs(r.exact - tq) / abs(tq)))
                 worst_dd = max(worst_dd, float(abs(d.exact - tq) / abs(tq)))
         out["max_rel_err_vs_qd"] = {"auto_learned": worst, "fixed_dd": worst_dd}
+        # the ideal per-instance choice: FP64 wherever it meets tau against
+        # QD, DD elsewhere (needs the QD values, so it bounds what any
+        # selector can gain on this workload)
+        f64 = tor.tor_eval_batched(b, tiers="fp64")
+        ideal = ["fp64" if q.exact != 0 and abs(f.exact - q.exact) <= tau * abs(q.exact) else "dd"
+                 for f, q in zip(f64, ref)]
+        s_id = timed(lambda: tor.tor_eval_batched(b, tiers=ideal, graph=True, sync=False), steps)
+        nf = sum(1 for x in ideal if x == "fp64")
+        out["ideal_choice"] = {"s": s_id, "n_fp64": nf, "n_dd": count - nf,
+                               "gain_vs_fixed_dd": s_dd / s_id}
+        print(f"[bench] batched ideal choice: {s_id * 1e3:.1f} ms ({nf} FP64)", file=sys.stderr,
+              flush=True)
     # the same comparison at further accuracy targets (one timed call of the
     # bound-estimate-only selector each: it is the slow one)
     for t2 in extra_taus:
@@ -388,6 +401,8 @@ def main():
                     help="also run the n = 36 precision-stress leg (about a minute: QD reference)")
     ap.add_argument("--mcmc-only", action="store_true",
                     help="run only the sampler leg and print its JSON object (for profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched leg and print its JSON object (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="first copy this many bytes device-to-device (a known-size kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
@@ -414,6 +429,11 @@ def main():
     if args.mcmc_only:
         print(json.dumps({"mcmc": mcmc_leg(tor, max(args.mcmc_chains, 1), args.mcmc_steps,
                                            args.mcmc_reps)}), flush=True)
+        return
+    if args.batch_only:
+        extra = [float(x) for x in args.batch_taus.split(",") if x.strip()]
+        print(json.dumps({"batched": batched_leg(tor, max(args.batch, 1), args.tau, args.batch_steps,
+                                                 args.batch_check, extra)}), flush=True)
         return
 
     n = args.n
