@@ -87,6 +87,8 @@ hipError_t launch_expand(int tier, const void* in_mat, const void* in_g, const i
 // launch_expand calls would number them, with the same values.  0 bytes:
 // not available for these arguments; launches need bytes <= EXPAND_MULTI_LDS_MAX.
 constexpr size_t EXPAND_MULTI_LDS_MAX = 48 * 1024;
+// with the staged input state (three workgroups per 160 KiB CU)
+constexpr size_t EXPAND_MULTI_STAGE_LDS_MAX = 53 * 1024;
 size_t expand_multi_lds_bytes(int tier, int s, int K);
 hipError_t launch_expand_multi(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
                                int s, int K, int nst, void* out_mat, void* out_g, int32_t* out_m,

@@ -308,8 +308,10 @@ __global__ __launch_bounds__(256) void expand_kernel(const typename TT::R* __res
 // significant, as K single-level expansions would number them).  The
 // operations and their operands are those of expand_kernel, so the
 // descendants are bit-for-bit the same; only the intermediate states stay
-// out of HBM.  LDS (dynamic, expand_multi_lds_bytes): the states of levels
-// 1 .. K-1, the pivot column of the widest level, pivots, g and |Z|.
+// out of HBM.  LDS (dynamic, expand_multi_lds_bytes): with `stage`, first
+// a copy of the input state (read from HBM once, coalesced, instead of by
+// the scattered reads of level 0); then the states of levels 1 .. K-1, the
+// pivot column of the widest level, pivots, g and |Z|.
 __host__ __device__ inline size_t expand_multi_vals(int s, int K) {
   size_t v = 0;
   for (int j = 1; j < K; ++j) v += ((size_t)1 << j) * psize(s - j);
@@ -328,14 +330,22 @@ __global__ __launch_bounds__(256) void expand_multi_kernel(const typename TT::R*
                                                            typename TT::R* __restrict__ out_mat,
                                                            typename TT::R* __restrict__ out_g,
                                                            int32_t* __restrict__ out_m,
-                                                           int32_t* __restrict__ status) {
+                                                           int32_t* __restrict__ status, int stage) {
   using R = typename TT::R;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* lds = reinterpret_cast<R*>(smem_raw);
   const int z = blockIdx.x;
   const int tid = (int)threadIdx.x;
-  // carve: level states (1 .. K-1), u0 | u1, pivots, g; then |Z| as int32
+  // carve: [input state], level states (1 .. K-1), u0 | u1, pivots, g; then
+  // |Z| as int32
+  const R* T0 = in_mat + (size_t)z * psize(s);
   size_t off = 0;
+  if (stage) {
+    for (int e = tid; e < psize(s); e += 256) lds[e] = T0[e];
+    T0 = lds;
+    off = psize(s);
+    __syncthreads();
+  }
   R* lvl[3] = {nullptr, nullptr, nullptr};
   for (int j = 1; j < K; ++j) {
     lvl[j] = lds + off;
@@ -351,7 +361,6 @@ __global__ __launch_bounds__(256) void expand_multi_kernel(const typename TT::R*
   R* spv = su1 + umax;                  // 3 per state of the widest level
   R* sg = spv + 3 * (1 << (K - 1));     // g of two consecutive levels, 2^K entries each
   int32_t* sm = reinterpret_cast<int32_t*>(sg + 2 * (1 << K));  // |Z|, likewise
-  const R* T0 = in_mat + (size_t)z * psize(s);
   for (int j = 0; j < K; ++j) {
     const int sj = s - j;                // modes of the states of level j
     const int nsj = 1 << j;
@@ -981,25 +990,34 @@ size_t expand_multi_lds_bytes(int tier, int s, int K) {
   return expand_multi_vals(s, K) * schur_value_bytes(tier) + 2 * ((size_t)1 << K) * sizeof(int32_t);
 }
 
+// Whether a launch stages its input state in LDS: where the copy still
+// leaves three workgroups room on a CU.
+static bool expand_multi_stage(int tier, int s, int K) {
+  return expand_multi_lds_bytes(tier, s, K) + (size_t)psize(s) * schur_value_bytes(tier) <=
+         EXPAND_MULTI_STAGE_LDS_MAX;
+}
+
 hipError_t launch_expand_multi(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
                                int s, int K, int nst, void* out_mat, void* out_g, int32_t* out_m,
                                int32_t* status, hipStream_t st) {
   if (nst <= 0) return hipSuccess;
-  const size_t lds = expand_multi_lds_bytes(tier, s, K);
+  size_t lds = expand_multi_lds_bytes(tier, s, K);
   if (lds == 0 || lds > EXPAND_MULTI_LDS_MAX) return hipErrorInvalidValue;
+  const int stage = expand_multi_stage(tier, s, K) ? 1 : 0;
+  if (stage) lds += (size_t)psize(s) * schur_value_bytes(tier);
   const dim3 grid(nst), block(256);
   switch (tier) {
     case TOR_FP64:
       hipLaunchKernelGGL(expand_multi_kernel<TierF64>, grid, block, lds, st, (const double*)in_mat,
-                         (const double*)in_g, in_m, s, K, (double*)out_mat, (double*)out_g, out_m, status);
+                         (const double*)in_g, in_m, s, K, (double*)out_mat, (double*)out_g, out_m, status, stage);
       break;
     case TOR_DD:
       hipLaunchKernelGGL(expand_multi_kernel<TierDD>, grid, block, lds, st, (const dd*)in_mat,
-                         (const dd*)in_g, in_m, s, K, (dd*)out_mat, (dd*)out_g, out_m, status);
+                         (const dd*)in_g, in_m, s, K, (dd*)out_mat, (dd*)out_g, out_m, status, stage);
       break;
     default:
       hipLaunchKernelGGL(expand_multi_kernel<TierQD>, grid, block, lds, st, (const qd*)in_mat,
-                         (const qd*)in_g, in_m, s, K, (qd*)out_mat, (qd*)out_g, out_m, status);
+                         (const qd*)in_g, in_m, s, K, (qd*)out_mat, (qd*)out_g, out_m, status, stage);
   }
   return hipGetLastError();
 }
