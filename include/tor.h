@@ -46,8 +46,13 @@ extern "C" {
 #define TOR_ENOMEM (-4)       /* device allocation failed */
 #define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan */
 
-/* Largest n accepted (subset masks are 64-bit; factor storage in LDS). */
-#define TOR_NMAX 48
+/* Largest n accepted: the paper's largest instance (N = 50, a 100 x 100
+ * matrix, Sec. 7).  Subset masks are 64-bit.  The Schur path keeps a
+ * frontier and chunks sized for it (at n = 50 about 10 GB in FP64, 26 GB in
+ * DD, 80 GB in QD of device memory); the bordered kernel keeps the factor in
+ * LDS and answers TOR_EUNSUPPORTED where a tier x n does not fit (DD beyond
+ * n = 49, QD beyond n = 34). */
+#define TOR_NMAX 50
 
 /* Precision tiers (Sec. 5.1-5.4; the paper's 128-bit tier corresponds to
  * TOR_DD and its 256-bit tier to TOR_QD, as in Table 5). */

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libtor_hip.so")
 TOR_OK, TOR_EINVAL, TOR_ENOTPD, TOR_EHIP, TOR_ENOMEM, TOR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO = 0, 1, 2, -1
 TOR_ALGO_AUTO, TOR_ALGO_BORDER, TOR_ALGO_SCHUR = 0, 1, 2
-TOR_NMAX = 48
+TOR_NMAX = 50
 TOR_FLAG_TIME_KERNEL = 1
 TOR_FLAG_GRAPH = 2
 

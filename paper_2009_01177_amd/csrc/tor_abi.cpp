@@ -346,6 +346,14 @@ void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
   int D_s = p->D_m < 10 ? p->D_m : 10;
   while (D_s > 0 && ((size_t)R << D_s) * psz(n - D_s) * p->rb > ((size_t)1 << 30)) --D_s;
   if (p->D_m - D_s > LT) D_s = p->D_m - LT;
+  // large n: the kept frontier doubles with every mode while the chunk
+  // stays put, so trade frontier for chunk (up to 2^22 middle states) while
+  // the frontier is the larger of the two
+  auto frontier_bytes = [&](int d) { return ((size_t)R << d) * psz(n - d) * p->rb; };
+  while (D_s > 10 && LT < 22 && frontier_bytes(D_s) > ((size_t)2 << LT) * psz(p->s_m) * p->rb) {
+    ++LT;
+    D_s = p->D_m - LT;
+  }
   p->D_s = D_s;
   p->Dl = p->D_m - D_s;
   p->Ns = (size_t)R << D_s;
@@ -355,8 +363,10 @@ void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
   p->nchunks = (int)((p->Ns + cr - 1) / cr);
   p->mids = cr << p->Dl;
 
+  // levels in the ping-pong buffers: the root, the top levels above D_s
+  // (depth D_s itself goes to the kept frontier) and a chunk's levels
   size_t lvl_vals = (size_t)R * psz(n);
-  for (int j = 1; j <= D_s; ++j) lvl_vals = std::max(lvl_vals, ((size_t)R << j) * psz(n - j));
+  for (int j = 1; j < D_s; ++j) lvl_vals = std::max(lvl_vals, ((size_t)R << j) * psz(n - j));
   for (int j = 1; j <= p->Dl; ++j) lvl_vals = std::max(lvl_vals, (cr << j) * psz(n - D_s - j));
   const size_t lvl_states = std::max(p->Ns, p->mids);
 

@@ -55,9 +55,22 @@ def test_sampled_terms_qd_largest_factor_in_lds(tor):
 
 
 @pytest.mark.parametrize("tier,tol", [("fp64", 1e-12), ("dd", 1e-27)])
-def test_sampled_terms_at_the_largest_n(tor, tier, tol):
+def test_sampled_terms_at_n48(tor, tier, tol):
     O = g.random_instance(48, 4848, M=60)
     _sampled(tor, O, 48, tier, 40, 48, tol)
+
+
+def test_sampled_terms_at_the_largest_n(tor):
+    """n = 50 (TOR_NMAX): FP64 single-subset terms against the oracle; the
+    double-double factor of a 100 x 100 matrix (164 KB) does not fit the
+    bordered kernel's LDS and is refused with TOR_EUNSUPPORTED."""
+    import paper_2009_01177_amd._lib as L
+    assert L.TOR_NMAX == 50
+    O = g.random_instance(50, 5050, M=60)
+    _sampled(tor, O, 50, "fp64", 40, 50, 1e-12)
+    with pytest.raises(tor.TorError) as e:
+        tor.tor_debug_sampled_terms(O, np.array([1], dtype=np.uint64), tier="dd")
+    assert e.value.code == -5
 
 
 def _block_state(n, seed):

@@ -140,3 +140,22 @@ def test_a_share_of_the_benchmark_instance_against_the_oracle(tor):
         assert r.status == 0
         assert float(abs(r.exact - want)) <= TOL[tier] * sabs, tier
         assert abs(float(r.abs_exact) - sabs) <= 1e-12 * sabs
+
+
+@pytest.mark.parametrize("tier", ["fp64", "dd", "qd"])
+def test_a_part_at_the_largest_n(tor, tier):
+    # n = 50 (the paper's largest instance size) through the Schur path: the
+    # part of 2^17 whose decisions on modes 0..16 are a seeded code (2^33
+    # subsets), of a product of 1- and 2-mode states whose first 17 modes are
+    # whole blocks, against its closed form (prefix blocks' terms times the
+    # other blocks' Torontonians, each at 60 digits)
+    from test_parts_host import part_closed_form, product_state_in_order
+    n, k = 50, 17
+    O, spans = product_state_in_order(n, k, 5017)
+    code = int(np.random.default_rng(k).integers(1 << k))
+    want, sabs = part_closed_form(O, spans, k, code)
+    print(f"[parts] n=50 tier={tier} part {code} of 2^{k}", flush=True)
+    r = tor.tor_eval_part(O, code, 1 << k, tier=tier)
+    assert r.status == 0
+    assert float(abs(r.exact - want) / sabs) <= TOL[tier]
+    assert abs(float(r.abs_exact) - float(sabs)) <= 1e-12 * float(sabs)
