@@ -147,8 +147,10 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
  * of two.  The definition does not depend on the tier or the options.
  *   O, n, ld, tier, opt, stream   as tor_eval (opt->algo AUTO or SCHUR)
  *   part, nparts   0 <= part < nparts; nparts <= 2^d where d is the depth at
- *                  which the evaluation keeps its frontier (up to 10; fewer
- *                  for small n), else TOR_EINVAL; n = 0 allows nparts = 1
+ *                  which the evaluation keeps its frontier (10 for most n;
+ *                  fewer for small n, more past n = 45: 18 at n = 50 in
+ *                  FP64 and DD, 19 in QD), else TOR_EINVAL; n = 0 allows
+ *                  nparts = 1
  *   out            host: tor = the part's signed sum, abs_sum its sum of
  *                  magnitudes, err_bound and status as tor_eval
  * Synchronous. */
