@@ -322,10 +322,24 @@ def small_leg(tor, reps: int = 20):
     ref = oracle.tor(O)
     out["oracle_s"] = time.perf_counter() - t
     out["oracle_threads"] = ref["threads"]
+    b1 = tor.Batch([O])
     for tier in ("fp64", "dd"):
         ms, _, res = time_tier(tor, Od, tier, reps, 2)
         out[tier] = {"ms": ms, "err_over_sabs": float(abs(res.exact - ref["tor"]) / ref["abs_sum"])}
-    print(f"[bench] n=16: fp64 {out['fp64']['ms']:.3f} ms, dd {out['dd']['ms']:.3f} ms, oracle "
+        # the same evaluation captured once as a HIP graph and replayed back
+        # to back, its result left on the device (no host round trip)
+        for _ in range(2):
+            tor.tor_eval_batched(b1, tiers=tier, graph=True, sync=False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            tor.tor_eval_batched(b1, tiers=tier, graph=True, sync=False)
+        torch.cuda.synchronize()
+        out[tier]["graph_replay_ms"] = (time.perf_counter() - t) / reps * 1e3
+        rg = tor.tor_eval_batched(b1, tiers=tier, graph=True)[0]
+        out[tier]["graph_err_over_sabs"] = float(abs(rg.exact - ref["tor"]) / ref["abs_sum"])
+    print(f"[bench] n=16: fp64 {out['fp64']['ms']:.3f} ms, dd {out['dd']['ms']:.3f} ms (graph replay "
+          f"{out['fp64']['graph_replay_ms']:.3f} / {out['dd']['graph_replay_ms']:.3f} ms), oracle "
           f"{out['oracle_s']:.2f} s", file=sys.stderr, flush=True)
     return out
 
