@@ -379,6 +379,16 @@ uint64_t tor_kth_mask(int32_t N, int32_t c, uint64_t k);
  * 0 <= d <= min(n, 30). */
 int tor_plan_items(int32_t n, int32_t d, uint64_t* out);
 
+/* Device workspace that one evaluation of an n-mode instance (tor_eval,
+ * tor_eval_part) needs in `tier`: the Schur path's kept frontier of the
+ * subset tree (Eq. 2), its per-chunk level buffers and partial sums
+ * (the paper sizes its per-process storage in Sec. 4.2; here it is the
+ * plan the library allocates by).  Host only, no GPU needed.
+ *   bottom_modes  0 (the library's choice) or as tor_options_t
+ *   bytes         host, out
+ * TOR_EINVAL for n outside 0..TOR_NMAX, an unknown tier or bottom_modes < 0. */
+int tor_workspace_bytes(int32_t n, int32_t tier, int32_t bottom_modes, uint64_t* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -396,6 +396,14 @@ def tor_kth_mask(N: int, c: int, k: int) -> int:
     return int(lib().tor_kth_mask(int(N), int(c), int(k)))
 
 
+def tor_workspace_bytes(n: int, tier="dd", bottom_modes: int = 0) -> int:
+    """Device bytes one evaluation of an n-mode instance allocates (host only)."""
+    b = ctypes.c_uint64(0)
+    check(lib().tor_workspace_bytes(int(n), tier_id(tier), int(bottom_modes), ctypes.byref(b)),
+          "tor_workspace_bytes")
+    return int(b.value)
+
+
 def tor_plan_items(n: int, d: int) -> np.ndarray:
     out = np.zeros(1 << d, dtype=np.uint64)
     check(lib().tor_plan_items(int(n), int(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),

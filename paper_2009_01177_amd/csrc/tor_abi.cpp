@@ -965,6 +965,19 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
   return out->status;
 }
 
+int tor_workspace_bytes(int32_t n, int32_t tier, int32_t bottom_modes, uint64_t* bytes) {
+  if (bytes == nullptr || n < 0 || n > TOR_NMAX || bottom_modes < 0) return TOR_EINVAL;
+  if (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD) return TOR_EINVAL;
+  if (n == 0) {
+    *bytes = 0;
+    return TOR_OK;
+  }
+  SchurPlan p;
+  plan_schur(tier, n, 1, bottom_modes, &p);
+  *bytes = p.bytes;
+  return TOR_OK;
+}
+
 double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches) {
   Workspace* w = nullptr;
   if (get_ws(&w) != TOR_OK) return -1.0;

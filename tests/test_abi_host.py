@@ -168,3 +168,24 @@ def test_eval_part_argument_checks_need_no_gpu(L):
     assert L.tor_eval_part(None, 0, 0, 1, None, None, 0, 2, ctypes.byref(out)) == E
     assert L.tor_eval_part(None, 0, 0, 1, None, None, 0, 1, ctypes.byref(out)) == 0
     assert out.tor[0] == 1.0
+
+
+def test_workspace_bytes_needs_no_gpu(L):
+    # the device workspace one evaluation allocates: the n = 30 benchmark
+    # instance needs about 2 GB in DD; at n = 50 (TOR_NMAX) every tier fits
+    # well inside one 288 GB device, DD in about 26 GB
+    import paper_2009_01177_amd as t
+    from paper_2009_01177_amd import _lib
+    GB = 1e9
+    assert 1 * GB < t.tor_workspace_bytes(30, "dd") < 4 * GB
+    sizes = {tier: t.tor_workspace_bytes(50, tier) for tier in ("fp64", "dd", "qd")}
+    assert sizes["fp64"] < 16 * GB and sizes["dd"] < 32 * GB and sizes["qd"] < 100 * GB, sizes
+    assert sizes["fp64"] < sizes["dd"] < sizes["qd"]
+    for n in range(1, _lib.TOR_NMAX + 1):
+        assert t.tor_workspace_bytes(n, "qd") < 100 * GB, n
+    assert t.tor_workspace_bytes(0, "dd") == 0
+    b = ctypes.c_uint64(0)
+    assert L.tor_workspace_bytes(_lib.TOR_NMAX + 1, _lib.TOR_DD, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
+    assert L.tor_workspace_bytes(10, 7, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
+    assert L.tor_workspace_bytes(10, _lib.TOR_DD, -1, ctypes.byref(b)) == _lib.TOR_EINVAL
+    assert L.tor_workspace_bytes(10, _lib.TOR_DD, 0, None) == _lib.TOR_EINVAL
