@@ -148,8 +148,9 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
  *   O, n, ld, tier, opt, stream   as tor_eval (opt->algo AUTO or SCHUR)
  *   part, nparts   0 <= part < nparts; nparts <= 2^d where d is the depth at
  *                  which the evaluation keeps its frontier (10 for most n;
- *                  fewer for small n, more past n = 45: 18 at n = 50 in
- *                  FP64 and DD, 19 in QD), else TOR_EINVAL; n = 0 allows
+ *                  fewer below n = 22; one more per mode from n = 42 in
+ *                  FP64, 40 in DD and 38 in QD, up to 18 at n = 50 in FP64
+ *                  and DD and 19 in QD), else TOR_EINVAL; n = 0 allows
  *                  nparts = 1
  *   out            host: tor = the part's signed sum, abs_sum its sum of
  *                  magnitudes, err_bound and status as tor_eval
@@ -182,9 +183,14 @@ int tor_combine_parts(int32_t tier, int32_t n, const tor_result_t* parts, int32_
  *   opt       NULL or knobs (algo must be TOR_ALGO_AUTO or TOR_ALGO_SCHUR)
  *   out       device, batch results; status TOR_ENOTPD marks an instance
  *             whose I - O is not positive definite
- * The call waits for `stream` to drain, uploads the batch plan, then
- * enqueues the evaluation and returns without waiting for it.  With
- * TOR_AUTO instances it is synchronous: the tiers are chosen first, and a
+ * With fixed tiers the call is stream-ordered: it enqueues the plan's
+ * upload (from pinned memory, into one of four plan slots that are reused
+ * once the batch that last used them has finished) and the evaluation on
+ * `stream` and returns without waiting; a replay of a captured batch
+ * (TOR_FLAG_GRAPH) is one graph launch.  The device workspace is shared by
+ * every call on a device, so calls on different streams must be ordered by
+ * the caller.  With TOR_AUTO instances it is synchronous: the tiers are
+ * chosen first, and a
  * sample of the network's FP64 and DD choices whose predicted error lies
  * within 4 decades of tau (1/32 of them, at least one per tier;
  * TOR_SPOT_FRACTION and TOR_SPOT_WINDOW override) is re-evaluated one tier
@@ -383,11 +389,20 @@ int tor_plan_items(int32_t n, int32_t d, uint64_t* out);
  * tor_eval_part) needs in `tier`: the Schur path's kept frontier of the
  * subset tree (Eq. 2), its per-chunk level buffers and partial sums
  * (the paper sizes its per-process storage in Sec. 4.2; here it is the
- * plan the library allocates by).  Host only, no GPU needed.
+ * plan the library allocates by, rounded up to 2 MiB: the workspace grows
+ * to exactly this for the largest evaluation it has run).  Host only, no
+ * GPU needed.
  *   bottom_modes  0 (the library's choice) or as tor_options_t
  *   bytes         host, out
  * TOR_EINVAL for n outside 0..TOR_NMAX, an unknown tier or bottom_modes < 0. */
 int tor_workspace_bytes(int32_t n, int32_t tier, int32_t bottom_modes, uint64_t* bytes);
+
+/* Device workspace tor_eval_batched (and tor_mcmc) needs for `count`
+ * instances of n modes in one tier: a group whose plan would pass 4 GiB runs
+ * as sub-groups of equal size, so this is the largest sub-group's plan (a
+ * single instance needs its own plan, as tor_workspace_bytes).  Host only. */
+int tor_batch_workspace_bytes(int32_t n, int32_t tier, int32_t count, int32_t bottom_modes,
+                              uint64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -29,6 +29,7 @@ EXPORTS = (
     "tor_selector_set", "tor_selector_get", "tor_selector_save", "tor_selector_load",
     "tor_fallback_bits", "tor_select_tiers", "tor_last_select_stats",
     "tor_autotune", "tor_autotune_save", "tor_autotune_load", "tor_workspace_bytes",
+    "tor_batch_workspace_bytes",
 )
 
 TOR_NFEAT = 12
@@ -188,6 +189,8 @@ def lib():
     L.tor_plan_items.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_uint64)]
     L.tor_workspace_bytes.restype = ctypes.c_int
     L.tor_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.tor_batch_workspace_bytes.restype = ctypes.c_int
+    L.tor_batch_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_uint64)]
     _lib = L
     return L
 

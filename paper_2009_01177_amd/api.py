@@ -404,6 +404,15 @@ def tor_workspace_bytes(n: int, tier="dd", bottom_modes: int = 0) -> int:
     return int(b.value)
 
 
+def tor_batch_workspace_bytes(n: int, count: int, tier="dd", bottom_modes: int = 0) -> int:
+    """Device bytes the batched path needs for `count` instances of n modes
+    in one tier (host only)."""
+    b = ctypes.c_uint64(0)
+    check(lib().tor_batch_workspace_bytes(int(n), tier_id(tier), int(count), int(bottom_modes),
+                                          ctypes.byref(b)), "tor_batch_workspace_bytes")
+    return int(b.value)
+
+
 def tor_plan_items(n: int, d: int) -> np.ndarray:
     out = np.zeros(1 << d, dtype=np.uint64)
     check(lib().tor_plan_items(int(n), int(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),

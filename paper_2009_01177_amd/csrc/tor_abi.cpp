@@ -40,8 +40,20 @@ struct Workspace {
   tor_result_t* host_res = nullptr;  // pinned
   double* host_lev = nullptr;        // pinned, 4*(TOR_NMAX+1)
   std::map<std::pair<int, int>, ItemTable> tables;  // (n, d) -> prefix items
-  char* meta = nullptr;         // device copy of the batch plan (offsets, indices, tiers)
+  char* meta = nullptr;         // device copy of the selector's plan (synchronous uploads)
   size_t meta_cap = 0;
+  // ring of batch-plan slots for stream-ordered batches: a slot is reused
+  // only after the event recorded behind its last batch has completed
+  struct PlanSlot {
+    char* dev = nullptr;
+    char* host = nullptr;  // pinned staging of the upload
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool used = false;
+  };
+  static constexpr int NSLOT = 4;
+  PlanSlot slots[NSLOT];
+  int slot_next = 0;
   // captured batches (TOR_FLAG_GRAPH); each owns a private device copy of its
   // plan, since the shared plan buffer is rewritten by every later call
   struct GraphEntry {
@@ -93,6 +105,13 @@ int record_ev(Workspace* w, int k, hipStream_t s) {
   }
   TOR_HIP(hipEventRecord(w->evs[k], s));
   return TOR_OK;
+}
+
+// Device bytes the workspace allocates for a plan of `bytes`: the plan
+// rounded up to 2 MiB (the workspace grows to the largest plan seen).
+size_t workspace_capacity(size_t bytes) {
+  const size_t g = (size_t)2 << 20;
+  return (bytes + g - 1) / g * g;
 }
 
 // Release every captured graph and its plan copy (after the device has
@@ -154,8 +173,7 @@ int get_ws(Workspace** out) {
 
 int ensure_cap(Workspace* w, size_t bytes) {
   if (bytes <= w->cap) return TOR_OK;
-  size_t ncap = w->cap ? w->cap : (size_t)1 << 20;
-  while (ncap < bytes) ncap *= 2;
+  const size_t ncap = workspace_capacity(bytes);
   if (w->buf) {
     // the old buffer may still be in use by enqueued work
     TOR_HIP(hipDeviceSynchronize());
@@ -330,30 +348,17 @@ struct SchurPlan {
 
 size_t psz(int k) { return (size_t)k * (2 * k + 1); }
 
-void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
+// Lay out a plan whose chunks end in 2^LT middle states and whose kept
+// frontier is at depth D_s (D_m - LT <= D_s <= D_m).
+void plan_layout(int tier, int n, int R, int s_m, int s_b, int LT, int D_s, SchurPlan* p) {
   p->tier = tier;
   p->n = n;
   p->R = R;
-  if (sb_req <= 0) sb_req = tuned_bottom(n, tier);
-  schur_levels(tier, n, sb_req, &p->s_m, &p->s_b);
-  p->D_m = n - p->s_m;
+  p->s_m = s_m;
+  p->s_b = s_b;
+  p->D_m = n - s_m;
   p->rb = schur_value_bytes(tier);
   p->ab = acc_bytes(tier);
-  // middle states per chunk: about 1.5 GB of them at the last top level
-  int LT = 0;
-  while (LT < 22 && ((size_t)2 << LT) * psz(p->s_m) * p->rb <= ((size_t)3 << 29)) ++LT;
-  // keep depth D_s (at most 10, at most ~1 GB of states, at least D_m - LT)
-  int D_s = p->D_m < 10 ? p->D_m : 10;
-  while (D_s > 0 && ((size_t)R << D_s) * psz(n - D_s) * p->rb > ((size_t)1 << 30)) --D_s;
-  if (p->D_m - D_s > LT) D_s = p->D_m - LT;
-  // large n: the kept frontier doubles with every mode while the chunk
-  // stays put, so trade frontier for chunk (up to 2^22 middle states) while
-  // the frontier is the larger of the two
-  auto frontier_bytes = [&](int d) { return ((size_t)R << d) * psz(n - d) * p->rb; };
-  while (D_s > 10 && LT < 22 && frontier_bytes(D_s) > ((size_t)2 << LT) * psz(p->s_m) * p->rb) {
-    ++LT;
-    D_s = p->D_m - LT;
-  }
   p->D_s = D_s;
   p->Dl = p->D_m - D_s;
   p->Ns = (size_t)R << D_s;
@@ -388,6 +393,50 @@ void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
   p->bytes = c.off;
 }
 
+// The library's plan for R instances of n modes: chunks of about 1.5 GB of
+// middle states, the frontier kept at depth 10 where it fits in about 1 GB.
+void plan_schur(int tier, int n, int R, int sb_req, SchurPlan* p) {
+  if (sb_req <= 0) sb_req = tuned_bottom(n, tier);
+  int s_m = 0, s_b = 0;
+  schur_levels(tier, n, sb_req, &s_m, &s_b);
+  const int D_m = n - s_m;
+  const size_t rb = schur_value_bytes(tier);
+  // middle states per chunk: about 1.5 GB of them at the last top level
+  int LT = 0;
+  while (LT < 22 && ((size_t)2 << LT) * psz(s_m) * rb <= ((size_t)3 << 29)) ++LT;
+  // keep depth D_s (at most 10, at most ~1 GB of states, at least D_m - LT)
+  int D_s = D_m < 10 ? D_m : 10;
+  while (D_s > 0 && ((size_t)R << D_s) * psz(n - D_s) * rb > ((size_t)1 << 30)) --D_s;
+  if (D_m - D_s > LT) D_s = D_m - LT;
+  // large n: the kept frontier doubles with every mode while the chunk
+  // stays put, so trade frontier for chunk (up to 2^22 middle states) while
+  // the frontier is the larger of the two
+  auto frontier_bytes = [&](int d) { return ((size_t)R << d) * psz(n - d) * rb; };
+  while (D_s > 10 && LT < 22 && frontier_bytes(D_s) > ((size_t)2 << LT) * psz(s_m) * rb) {
+    ++LT;
+    D_s = D_m - LT;
+  }
+  plan_layout(tier, n, R, s_m, s_b, LT, D_s, p);
+}
+
+// A plan within max_bytes: the library's plan when it fits, else the one
+// with the largest chunks that fits (frontier at the least depth they
+// allow).  false when none does.
+bool plan_schur_fit(int tier, int n, int R, int sb_req, size_t max_bytes, SchurPlan* p) {
+  plan_schur(tier, n, R, sb_req, p);
+  if (p->bytes <= max_bytes) return true;
+  const int s_m = p->s_m, s_b = p->s_b, D_m = p->D_m;
+  for (int LT = 22; LT >= 0; --LT) {
+    SchurPlan q;
+    plan_layout(tier, n, R, s_m, s_b, LT, std::max(0, D_m - LT), &q);
+    if (q.bytes <= max_bytes) {
+      *p = q;
+      return true;
+    }
+  }
+  return false;
+}
+
 // Fold nseg segments of seg_len partials each (a two-stage reduction when one
 // long segment is all there is).
 int fold(int tier, const void* part, int nseg, size_t seg_len, void* out, void* scratch, hipStream_t s) {
@@ -400,21 +449,23 @@ int fold(int tier, const void* part, int nseg, size_t seg_len, void* out, void* 
 // instance k; results go to out[out_index ? out_index[k] : k] (device).
 // With one instance, only the depth-D_s states [z_lo, z_hi) are expanded and
 // summed (a share of the evaluation; the whole of it by default).
-int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const int64_t* offs_dev,
-                        int64_t ld, const tor_options_t* opt, const int32_t* out_index,
-                        tor_result_t* out, bool timed, hipStream_t s, size_t z_lo = 0,
-                        size_t z_hi = SIZE_MAX) {
+// B is the plan's base (p.bytes of device memory), cus the device's compute
+// units; w (may be NULL) receives the kernel timing events and launch shape.
+int enqueue_schur_group(Workspace* w, char* B, int cus, const SchurPlan& p, const void* O,
+                        const int64_t* offs_dev, int64_t ld, const tor_options_t* opt,
+                        const int32_t* out_index, tor_result_t* out, bool timed, hipStream_t s,
+                        size_t z_lo = 0, size_t z_hi = SIZE_MAX) {
   const int tier = p.tier, n = p.n;
   const bool whole = z_lo == 0 && z_hi >= p.Ns;
   if (!whole && (p.R != 1 || z_lo >= z_hi || z_hi > p.Ns)) return TOR_EINVAL;
   if (whole) z_hi = p.Ns;
-  char* B = w->buf;
+  if (timed && !w) return TOR_EINVAL;
   uint32_t* cnt = (uint32_t*)(B + p.o_cnt);
   int32_t* status = (int32_t*)(cnt + 1);
   int occ = 0;
   TOR_HIP(leaf_occupancy(tier, p.s_b, &occ));
   if (occ < 1) return TOR_EUNSUPPORTED;
-  int grid = (opt && opt->grid > 0) ? opt->grid : occ * w->cus;
+  int grid = (opt && opt->grid > 0) ? opt->grid : occ * cus;
   if ((size_t)grid > p.mids) grid = (int)p.mids;
 
   TOR_HIP(launch_zero_words(cnt, 64, s));
@@ -488,9 +539,31 @@ int enqueue_schur_group(Workspace* w, const SchurPlan& p, const void* O, const i
     TOR_TRY(fold(tier, B + p.o_ds + ab * 2 * z_lo, 1, z_hi - z_lo, B + p.o_inst, B + p.o_rsc, s));
   const double err_rel = (double)(4 * n * n + n + 8) * unit_roundoff(tier);
   TOR_HIP(launch_finalize_batch(tier, B + p.o_inst, p.R, out_index, n, err_rel, out, s));
-  w->last_d = p.D_m;
-  w->last_grid = grid;
+  if (w) {
+    w->last_d = p.D_m;
+    w->last_grid = grid;
+  }
   return TOR_OK;
+}
+
+// Largest plan a batch group may take before it is split; a single
+// instance takes what its own plan needs.
+constexpr size_t GROUP_BUDGET = (size_t)4 << 30;
+
+// Instances per sub-group for a group of R instances of n modes: the most
+// whose plan stays within GROUP_BUDGET (at least one).
+int group_share(int tier, int n, int R, int sb) {
+  SchurPlan p;
+  plan_schur(tier, n, R, sb, &p);
+  if (p.bytes <= GROUP_BUDGET || R <= 1) return std::max(R, 1);
+  int lo = 1, hi = R - 1;  // plan(lo) fits or lo == 1; plan(R) does not
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 1) / 2;
+    plan_schur(tier, n, mid, sb, &p);
+    if (p.bytes <= GROUP_BUDGET) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // A batch grouped by (n, tier).
@@ -516,6 +589,35 @@ int upload_meta(Workspace* w, const void* src, size_t bytes, hipStream_t s) {
   return TOR_OK;
 }
 
+// Stage a batch plan in the next slot of the ring: wait for the slot's
+// previous batch only (its event), copy the plan to pinned memory and enqueue
+// its upload on s.  The caller records the slot's event behind the batch.
+int stage_plan(Workspace* w, const void* src, size_t bytes, hipStream_t s, Workspace::PlanSlot** out) {
+  Workspace::PlanSlot& sl = w->slots[w->slot_next];
+  w->slot_next = (w->slot_next + 1) % Workspace::NSLOT;
+  if (!sl.ev) TOR_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+  if (sl.used) {
+    TOR_HIP(hipEventSynchronize(sl.ev));
+    sl.used = false;
+  }
+  if (bytes > sl.cap) {
+    if (sl.dev) TOR_HIP(hipFree(sl.dev));
+    if (sl.host) TOR_HIP(hipHostFree(sl.host));
+    sl.dev = nullptr;
+    sl.host = nullptr;
+    sl.cap = 0;
+    size_t cap = 4096;
+    while (cap < bytes) cap *= 2;
+    TOR_HIP(hipMalloc((void**)&sl.dev, cap));
+    TOR_HIP(hipHostMalloc((void**)&sl.host, cap, hipHostMallocDefault));
+    sl.cap = cap;
+  }
+  memcpy(sl.host, src, bytes);
+  TOR_HIP(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, s));
+  *out = &sl;
+  return TOR_OK;
+}
+
 // Enqueue every group of a batch whose plan is at `plan` (device).
 int enqueue_batch(Workspace* w, const char* plan, const std::vector<BatchGroup>& groups,
                   const std::vector<SchurPlan>& plans, const std::vector<size_t>& meta_off,
@@ -528,7 +630,8 @@ int enqueue_batch(Workspace* w, const char* plan, const std::vector<BatchGroup>&
     const BatchGroup& g = groups[gi];
     const int64_t* offs = (const int64_t*)(plan + meta_off[gi]);
     const int32_t* oidx = (const int32_t*)(offs + g.idx.size());
-    TOR_TRY(enqueue_schur_group(w, plans[gi], O_packed, offs, 2 * (int64_t)g.n, opt, oidx, out, false, s));
+    TOR_TRY(enqueue_schur_group(w, w->buf, w->cus, plans[gi], O_packed, offs, 2 * (int64_t)g.n, opt, oidx, out,
+                                false, s));
   }
   return TOR_OK;
 }
@@ -598,12 +701,27 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
     }
     groups[it->second].idx.push_back(k);
   }
+  // groups whose plan would outgrow the group budget run as several
+  // sub-groups of equal size
+  const int sb_opt = opt ? opt->bottom_modes : 0;
+  {
+    std::vector<BatchGroup> split;
+    for (BatchGroup& g : groups) {
+      const int R = (int)g.idx.size();
+      const int per = group_share(g.tier, g.n, R, sb_opt);
+      for (int a = 0; a < R; a += per) {
+        BatchGroup h{g.n, g.tier, {}};
+        h.idx.assign(g.idx.begin() + a, g.idx.begin() + std::min(R, a + per));
+        split.push_back(std::move(h));
+      }
+    }
+    groups.swap(split);
+  }
   // plans, one workspace size for all groups (they run one after another)
   std::vector<SchurPlan> plans(groups.size());
   size_t need = 0;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
-    plan_schur(groups[gi].tier, groups[gi].n, (int)groups[gi].idx.size(), opt ? opt->bottom_modes : 0,
-               &plans[gi]);
+    plan_schur(groups[gi].tier, groups[gi].n, (int)groups[gi].idx.size(), sb_opt, &plans[gi]);
     need = std::max(need, plans[gi].bytes);
   }
   TOR_TRY(ensure_cap(w, need));
@@ -665,9 +783,18 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
     TOR_HIP(hipGraphLaunch(ge.exec, s));
     return TOR_OK;
   }
-  if (!meta.empty()) TOR_TRY(upload_meta(w, meta.data(), meta.size(), s));
-  return enqueue_batch(w, w->meta, groups, plans, meta_off, triv_off, (int)triv_idx.size(), O_packed,
-                       opt, out, s);
+  // eager: the plan goes into the next ring slot with an asynchronous copy;
+  // nothing waits for the stream unless that slot's previous batch is
+  // still running
+  Workspace::PlanSlot* sl = nullptr;
+  if (!meta.empty()) TOR_TRY(stage_plan(w, meta.data(), meta.size(), s, &sl));
+  TOR_TRY(enqueue_batch(w, sl ? sl->dev : nullptr, groups, plans, meta_off, triv_off, (int)triv_idx.size(),
+                        O_packed, opt, out, s));
+  if (sl) {
+    TOR_HIP(hipEventRecord(sl->ev, s));
+    sl->used = true;
+  }
+  return TOR_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -882,7 +1009,7 @@ int enqueue_schur(Workspace* w, const void* O, int n, int64_t ld, int tier,
   const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
   w->ev_pairs = 0;
   tor_result_t* dres = (tor_result_t*)(w->buf + p.o_res);
-  TOR_TRY(enqueue_schur_group(w, p, O, nullptr, ld, opt, nullptr, dres, timed, s));
+  TOR_TRY(enqueue_schur_group(w, w->buf, w->cus, p, O, nullptr, ld, opt, nullptr, dres, timed, s));
   ro->dres = dres;
   ro->red = w->buf + p.o_inst;
   ro->ncols = 2;
@@ -930,6 +1057,11 @@ int tor_shutdown(void) {
       for (hipEvent_t e : w->evs) (void)hipEventDestroy(e);
       drop_graphs(w);
       if (w->meta) (void)hipFree(w->meta);
+      for (auto& sl : w->slots) {
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.ev) (void)hipEventDestroy(sl.ev);
+      }
       if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
       if (w->aux) (void)hipFree(w->aux);
       (void)hipSetDevice(cur);
@@ -974,7 +1106,21 @@ int tor_workspace_bytes(int32_t n, int32_t tier, int32_t bottom_modes, uint64_t*
   }
   SchurPlan p;
   plan_schur(tier, n, 1, bottom_modes, &p);
-  *bytes = p.bytes;
+  *bytes = workspace_capacity(p.bytes);
+  return TOR_OK;
+}
+
+int tor_batch_workspace_bytes(int32_t n, int32_t tier, int32_t count, int32_t bottom_modes, uint64_t* bytes) {
+  if (bytes == nullptr || n < 0 || n > TOR_NMAX || count < 0 || bottom_modes < 0) return TOR_EINVAL;
+  if (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD) return TOR_EINVAL;
+  if (n == 0 || count == 0) {
+    *bytes = 0;
+    return TOR_OK;
+  }
+  const int per = group_share(tier, n, count, bottom_modes);
+  SchurPlan p;
+  plan_schur(tier, n, per, bottom_modes, &p);
+  *bytes = workspace_capacity(p.bytes);
   return TOR_OK;
 }
 
@@ -1013,7 +1159,8 @@ int tor_eval_part(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_
   const bool timed = opt && (opt->flags & TOR_FLAG_TIME_KERNEL);
   w->ev_pairs = 0;
   tor_result_t* dres = (tor_result_t*)(w->buf + p.o_res);
-  TOR_TRY(enqueue_schur_group(w, p, O, nullptr, ld, opt, nullptr, dres, timed, s, c_lo << sh, c_hi << sh));
+  TOR_TRY(enqueue_schur_group(w, w->buf, w->cus, p, O, nullptr, ld, opt, nullptr, dres, timed, s, c_lo << sh,
+                              c_hi << sh));
   TOR_HIP(hipMemcpyAsync(w->host_res, dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
   TOR_HIP(hipStreamSynchronize(s));
   if (w->ev_pairs > 0) TOR_TRY(collect_ev(w));
@@ -1073,9 +1220,6 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   Workspace* w = nullptr;
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
-  // the previous call on this stream may still read the plan buffer
-  TOR_HIP(hipStreamSynchronize(s));
-
   std::vector<int32_t> tier_of(batch);
   for (int k = 0; k < batch; ++k) tier_of[k] = tiers ? tiers[k] : TOR_AUTO;
   std::vector<double> pred;

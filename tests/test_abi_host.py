@@ -189,3 +189,47 @@ def test_workspace_bytes_needs_no_gpu(L):
     assert L.tor_workspace_bytes(10, 7, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
     assert L.tor_workspace_bytes(10, _lib.TOR_DD, -1, ctypes.byref(b)) == _lib.TOR_EINVAL
     assert L.tor_workspace_bytes(10, _lib.TOR_DD, 0, None) == _lib.TOR_EINVAL
+
+
+def test_workspace_bytes_is_the_allocated_capacity(L):
+    """The workspace grows to exactly the plan of the largest evaluation,
+    rounded up to 2 MiB, and that is what tor_workspace_bytes reports: at
+    n = 50 about 9.5 GB (FP64), 26 GB (DD), 79 GB (QD)."""
+    import paper_2009_01177_amd as t
+    from paper_2009_01177_amd import _lib
+    step = 2 << 20
+    for tier in ("fp64", "dd", "qd"):
+        prev = 0
+        for n in range(1, _lib.TOR_NMAX + 1):
+            b = t.tor_workspace_bytes(n, tier)
+            assert b > 0 and b % step == 0, (tier, n, b)
+            # a one-instance batch plans the same evaluation
+            assert t.tor_batch_workspace_bytes(n, 1, tier) == b, (tier, n)
+            prev = b
+    GB = 1e9
+    s50 = [t.tor_workspace_bytes(50, tier) / GB for tier in ("fp64", "dd", "qd")]
+    assert 9 < s50[0] < 10 and 25 < s50[1] < 27 and 78 < s50[2] < 81, s50
+
+
+def test_batch_groups_stay_within_their_budget(L):
+    """A batch group whose plan would pass 4 GiB runs as equal sub-groups:
+    at the sampler's default chunk (1 GiB of packed O_S) the batched path
+    plans at most 4 GiB for every N up to TOR_NMAX, unless one instance alone
+    needs more (then it plans exactly that instance)."""
+    import paper_2009_01177_amd as t
+    from paper_2009_01177_amd import _lib
+    budget = (4 << 30) + (2 << 20)
+    for tier in ("fp64", "dd", "qd"):
+        for N in range(1, _lib.TOR_NMAX + 1):
+            chunk = max(1, (1 << 26) // (4 * N * N))
+            b = t.tor_batch_workspace_bytes(N, chunk, tier)
+            single = t.tor_workspace_bytes(N, tier)
+            assert b <= max(budget, single), (tier, N, chunk, b, single)
+            if single > budget:
+                assert b == single, (tier, N)
+    assert t.tor_batch_workspace_bytes(0, 100, "dd") == 0
+    assert t.tor_batch_workspace_bytes(12, 0, "dd") == 0
+    b = ctypes.c_uint64(0)
+    assert L.tor_batch_workspace_bytes(12, 1, -1, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
+    assert L.tor_batch_workspace_bytes(12, 9, 1, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
+    assert L.tor_batch_workspace_bytes(12, 1, 1, 0, None) == _lib.TOR_EINVAL

@@ -111,3 +111,51 @@ def test_the_full_benchmark_batch_sampled(tor):
         q = tor.tor_eval(Os[k], tier="qd")
         assert float(abs(dd[k].exact - q.exact) / q.abs_exact) <= 1e-25, k
         assert float(abs(auto[k].exact - q.exact) / abs(q.exact)) <= 1e-3, k
+
+
+def _results_equal(a, b):
+    return [r.expansion for r in a] == [r.expansion for r in b]
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_fixed_tier_batches_return_before_their_work_ends(tor, graph):
+    """A fixed-tier batch is stream-ordered: the call returns while its
+    kernels still run (an event recorded right after it is not yet
+    complete), and the results are those of a synchronous call.  With
+    graph=True the second call is a replay of the cached graph."""
+    import torch
+    Os = [g.random_instance(26, 900 + i) for i in range(12)]
+    b = tor.Batch(Os)
+    ref = tor.tor_eval_batched(b, tiers="dd", graph=graph)
+    torch.cuda.synchronize()
+    b.out.zero_()
+    torch.cuda.synchronize()
+    tor.tor_eval_batched(b, tiers="dd", graph=graph, sync=False)
+    ev = torch.cuda.Event()
+    ev.record()
+    pending = not ev.query()
+    torch.cuda.synchronize()
+    from paper_2009_01177_amd.api import _results_from
+    got = _results_from(b.out[:b.batch].cpu().numpy())
+    print(f"[batched] graph={graph} returned before completion: {pending}", flush=True)
+    assert pending
+    assert _results_equal(got, ref)
+
+
+def test_back_to_back_eager_batches_keep_their_plans(tor):
+    """More eager batches in flight on one stream than there are plan slots,
+    each with its own plan and output: every result matches the batch's
+    synchronous evaluation bit for bit (a slot is reused only after the batch
+    that last used it has finished)."""
+    import torch
+    from paper_2009_01177_amd.api import _results_from
+    batches = [tor.Batch(_mixed(6 + k, 4, 14, 40 + k)) for k in range(9)]
+    refs = [tor.tor_eval_batched(bk, tiers="dd") for bk in batches]
+    for bk in batches:
+        bk.out.zero_()
+    torch.cuda.synchronize()
+    for bk in batches:
+        tor.tor_eval_batched(bk, tiers="dd", sync=False)
+    torch.cuda.synchronize()
+    for k, bk in enumerate(batches):
+        assert _results_equal(_results_from(bk.out[:bk.batch].cpu().numpy()), refs[k]), k
