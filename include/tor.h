@@ -385,6 +385,34 @@ uint64_t tor_kth_mask(int32_t N, int32_t c, uint64_t k);
  * 0 <= d <= min(n, 30). */
 int tor_plan_items(int32_t n, int32_t d, uint64_t* out);
 
+/* ---- Evaluation without device allocation -------------------------------
+ * For callers that cannot call hipMalloc: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation.  The library holds
+ * one fixed buffer of TOR_NOALLOC_SCRATCH_BYTES on every device it runs on,
+ * from the moment its code is loaded there until the process ends. */
+#define TOR_NOALLOC_SCRATCH_BYTES ((uint64_t)256 << 20)
+
+/* Tor(O) as tor_eval computes it through the Schur path (Sec. 3.1, Eq. 2),
+ * with every intermediate in the fixed buffer: no device or host memory is
+ * allocated (the first call on a device, or tor_init, looks up the
+ * buffer's device address).  Enqueued on `stream`; returns without waiting.
+ *   O, n, ld, tier  as tor_eval (default options: library's bottom size)
+ *   out             device, one tor_result_t, written by the last kernel
+ * n above tor_noalloc_nmax(tier) gives TOR_EUNSUPPORTED.  Where the plan
+ * tor_eval uses fits in the buffer the result is bit-for-bit tor_eval's;
+ * larger n run the same kernels in smaller chunks (same value within the
+ * tier's error bound).  Every call on a device shares that device's buffer,
+ * which keeps the last call's contents (what must start at zero is cleared
+ * by a kernel in the sequence): calls that overlap on one device (other
+ * streams, other threads) race and must be ordered by the caller.  Usable
+ * inside stream capture. */
+int tor_eval_noalloc(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
+                     tor_result_t* out);
+
+/* Largest n tor_eval_noalloc accepts in `tier` (the plan must fit in
+ * TOR_NOALLOC_SCRATCH_BYTES); TOR_EINVAL for an unknown tier.  Host only. */
+int32_t tor_noalloc_nmax(int32_t tier);
+
 /* Device workspace that one evaluation of an n-mode instance (tor_eval,
  * tor_eval_part) needs in `tier`: the Schur path's kept frontier of the
  * subset tree (Eq. 2), its per-chunk level buffers and partial sums

@@ -18,6 +18,7 @@ TOR_ALGO_AUTO, TOR_ALGO_BORDER, TOR_ALGO_SCHUR = 0, 1, 2
 TOR_NMAX = 50
 TOR_FLAG_TIME_KERNEL = 1
 TOR_FLAG_GRAPH = 2
+TOR_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 # Every symbol include/tor.h declares.
 EXPORTS = (
@@ -29,7 +30,7 @@ EXPORTS = (
     "tor_selector_set", "tor_selector_get", "tor_selector_save", "tor_selector_load",
     "tor_fallback_bits", "tor_select_tiers", "tor_last_select_stats",
     "tor_autotune", "tor_autotune_save", "tor_autotune_load", "tor_workspace_bytes",
-    "tor_batch_workspace_bytes",
+    "tor_batch_workspace_bytes", "tor_eval_noalloc", "tor_noalloc_nmax",
 )
 
 TOR_NFEAT = 12
@@ -191,6 +192,10 @@ def lib():
     L.tor_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(ctypes.c_uint64)]
     L.tor_batch_workspace_bytes.restype = ctypes.c_int
     L.tor_batch_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_uint64)]
+    L.tor_eval_noalloc.restype = ctypes.c_int
+    L.tor_eval_noalloc.argtypes = [vp, i32, i64, i32, vp, vp]
+    L.tor_noalloc_nmax.restype = i32
+    L.tor_noalloc_nmax.argtypes = [i32]
     _lib = L
     return L
 

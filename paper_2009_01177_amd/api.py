@@ -413,6 +413,29 @@ def tor_batch_workspace_bytes(n: int, count: int, tier="dd", bottom_modes: int =
     return int(b.value)
 
 
+def tor_noalloc_nmax(tier="dd") -> int:
+    """Largest n tor_eval_noalloc accepts in `tier` (host only)."""
+    v = int(lib().tor_noalloc_nmax(tier_id(tier)))
+    if v < 0:
+        check(v, "tor_noalloc_nmax")
+    return v
+
+
+def tor_eval_noalloc(O, tier="dd", stream=None, out=None):
+    """Tor(O) into the device tensor `out` (float64 [8], one tor_result_t;
+    allocated here when None) without any allocation inside the library;
+    enqueued on the stream, returns `out` without waiting."""
+    torch = _torch()
+    Od, n, ld = _device_o(O)
+    if out is None:
+        out = torch.zeros(8, dtype=torch.float64, device=Od.device)
+    if out.dtype != torch.float64 or out.numel() < 8 or not out.is_contiguous() or out.device != Od.device:
+        raise ValueError("out must be a contiguous float64 device tensor of at least 8 elements")
+    check(lib().tor_eval_noalloc(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), _stream_ptr(stream),
+                                 ctypes.c_void_p(out.data_ptr())), "tor_eval_noalloc")
+    return out
+
+
 def tor_plan_items(n: int, d: int) -> np.ndarray:
     out = np.zeros(1 << d, dtype=np.uint64)
     check(lib().tor_plan_items(int(n), int(d), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))),

@@ -1039,7 +1039,11 @@ const char* tor_strerror(int code) {
 
 int tor_init(void) {
   Workspace* w = nullptr;
-  return get_ws(&w);
+  TOR_TRY(get_ws(&w));
+  // the fixed buffer of tor_eval_noalloc: look up its device address now
+  void* base = nullptr;
+  int cus = 0;
+  return hip_err(noalloc_buffer(&base, &cus));
 }
 
 int tor_shutdown(void) {
@@ -1095,6 +1099,40 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
   if (w->ev_pairs > 0) TOR_TRY(collect_ev(w));
   *out = *w->host_res;
   return out->status;
+}
+
+int tor_eval_noalloc(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream, tor_result_t* out) {
+  if (out == nullptr) return TOR_EINVAL;
+  TOR_TRY(check_common(O, n, ld, tier));
+  if (n > tor_noalloc_nmax(tier)) return TOR_EUNSUPPORTED;
+  void* base = nullptr;
+  int cus = 0;
+  TOR_HIP(noalloc_buffer(&base, &cus));
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) return hip_err(launch_trivial_one(out, tier, s));
+  SchurPlan p;
+  if (!plan_schur_fit(tier, n, 1, 0, TOR_NOALLOC_SCRATCH_BYTES, &p)) return TOR_EUNSUPPORTED;
+  // the buffer keeps the last call's contents: the plan's counters and
+  // status word are cleared by a kernel inside the sequence, and every
+  // partial sum is written before it is read
+  return enqueue_schur_group(nullptr, (char*)base, cus, p, O, nullptr, ld, nullptr, nullptr, out, false, s);
+}
+
+int32_t tor_noalloc_nmax(int32_t tier) {
+  if (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD) return TOR_EINVAL;
+  static std::mutex mu;
+  static int cached[3] = {-1, -1, -1};
+  std::lock_guard<std::mutex> lk(mu);
+  if (cached[tier] < 0) {
+    int nmax = 0;
+    for (int n = 1; n <= TOR_NMAX; ++n) {
+      SchurPlan p;
+      if (!plan_schur_fit(tier, n, 1, 0, TOR_NOALLOC_SCRATCH_BYTES, &p)) break;
+      nmax = n;
+    }
+    cached[tier] = nmax;
+  }
+  return cached[tier];
 }
 
 int tor_workspace_bytes(int32_t n, int32_t tier, int32_t bottom_modes, uint64_t* bytes) {

@@ -109,4 +109,11 @@ hipError_t launch_mlp_grad(const double* th, const double* mean, const double* s
 hipError_t launch_adam(double* th, const double* grad, double* m, double* v, double lr, double b1,
                        double b2, double eps, int step, hipStream_t s);
 
+// The fixed device buffer of tor_eval_noalloc (TOR_NOALLOC_SCRATCH_BYTES per
+// device): its device address on the current device and the device's
+// compute units, looked up on the first call on each device.
+hipError_t noalloc_buffer(void** ptr, int* cus);
+// One trivial result (Tor = 1, the n = 0 case) written by a kernel.
+hipError_t launch_trivial_one(tor_result_t* out, int tier, hipStream_t s);
+
 }  // namespace tor
