@@ -71,9 +71,10 @@ def schur_node_flops(sp: int, tier: str) -> int:
 
 
 def acc_flops(tier: str) -> int:
-    """Accumulation of one term into a lane's signed and magnitude sums
-    (two_sum of the leading parts, low parts added in binary64)."""
-    return 2 * 7 if tier == "fp64" else 2 * 8
+    """Accumulation of one term into its lane's run for the term's size
+    parity (two_sum of the leading parts, low parts added in binary64); the
+    two runs give both the signed sum and the sum of magnitudes."""
+    return 7 if tier == "fp64" else 8
 
 
 def schur_flops(n: int, tier: str, dmin: int = 0) -> int:
@@ -311,6 +312,7 @@ def small_leg(tor, reps: int = 20):
     """The 16-mode lossless instance (65,536 subsets; launch-latency bound):
     ms per evaluation in FP64 and DD, and the binary128 oracle's full
     evaluation on the host beside it, with both errors over S_abs."""
+    import numpy as np
     import torch
     import gbs_inputs as g
     import oracle
@@ -336,6 +338,21 @@ def small_leg(tor, reps: int = 20):
             tor.tor_eval_batched(b1, tiers=tier, graph=True, sync=False)
         torch.cuda.synchronize()
         out[tier]["graph_replay_ms"] = (time.perf_counter() - t) / reps * 1e3
+        # each replay on its own: device time between events around the call,
+        # and the host time the call takes to return
+        dev, host = [], []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            h = time.perf_counter()
+            tor.tor_eval_batched(b1, tiers=tier, graph=True, sync=False)
+            host.append((time.perf_counter() - h) * 1e3)
+            e1.record()
+            torch.cuda.synchronize()
+            dev.append(e0.elapsed_time(e1))
+        out[tier]["graph_replay_device_ms"] = {"median": float(np.median(dev)), "max": float(np.max(dev))}
+        out[tier]["graph_call_host_ms"] = {"median": float(np.median(host)), "max": float(np.max(host))}
         rg = tor.tor_eval_batched(b1, tiers=tier, graph=True)[0]
         out[tier]["graph_err_over_sabs"] = float(abs(rg.exact - ref["tor"]) / ref["abs_sum"])
     print(f"[bench] n=16: fp64 {out['fp64']['ms']:.3f} ms, dd {out['dd']['ms']:.3f} ms (graph replay "
@@ -357,14 +374,20 @@ def stress_leg(tor, taus=(1e-3, 1e-6)):
     out = {"workload": "single Torontonian n=36: 100-mode GBS (Haar U, r=1.5, eta=0.5), 36 clicked "
                        "modes, O 72x72 complex128"}
     res = {}
+    n = O.shape[0] // 2
     for tier in ("fp64", "dd", "qd"):
         if tier != "qd":
             tor.tor_eval(Od, tier=tier)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        res[tier] = tor.tor_eval(Od, tier=tier)
+        res[tier] = tor.tor_eval(Od, tier=tier, time_kernel=True)
         torch.cuda.synchronize()
-        out[tier] = {"s": time.perf_counter() - t}
+        out[tier] = {"s": time.perf_counter() - t, "terms_per_s": float(1 << n) / (time.perf_counter() - t)}
+        kms, d_used, _, launches = tor.tor_last_kernel_ms()
+        if tier != "qd":
+            fl = kernel_flops(n, tier, "schur", d_used)
+            out[tier].update({"kernel_s": kms / 1e3, "launches": launches,
+                              "frac_fp64_peak": fl / (kms / 1e3) / 1e12 / PEAK_FP64_TFLOPS})
         print(f"[bench] n=36 {tier}: {out[tier]['s']:.3f} s", file=sys.stderr, flush=True)
     q = res["qd"]
     out["kappa"] = q.kappa
@@ -384,6 +407,33 @@ def stress_leg(tor, taus=(1e-3, 1e-6)):
             "source": "network" if int(src[0]) == 0 else "bound estimate", "s": sec,
             "rel_err_vs_qd": float(abs(r.exact - q.exact) / abs(q.exact))}
         print(f"[bench] n=36 tau={tau:g}: {out['selector'][repr(tau)]}", file=sys.stderr, flush=True)
+    return out
+
+
+def n40_leg(tor):
+    """The largest one-GPU workload: n = 40 of a 100-mode lossy state
+    (r ~ U[1.0, 1.6], transmission 0.3), 2^40 subsets in double-double, one
+    evaluation (after a one-time n = 40 FP64 warm-up of the workspace)."""
+    import torch
+    import gbs_inputs as g
+    O, _ = g.workload("n40_lossy")
+    Od = torch.from_numpy(O).to("cuda:0")
+    n = O.shape[0] // 2
+    tor.tor_eval(Od, tier="fp64")  # grows the workspace to the n = 40 plan
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = tor.tor_eval(Od, tier="dd", time_kernel=True)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    kms, d_used, grid, launches = tor.tor_last_kernel_ms()
+    fl = kernel_flops(n, "dd", "schur", d_used)
+    out = {"workload": "single Torontonian n=40: 100-mode lossy GBS (Haar U, r~U[1.0,1.6], eta=0.3), "
+                       "40 clicked modes, O 80x80 complex128", "tier": "dd", "s": sec,
+           "terms": 1 << n, "terms_per_s": float(1 << n) / sec, "kernel_s": kms / 1e3,
+           "launches": launches, "frac_fp64_peak": fl / (kms / 1e3) / 1e12 / PEAK_FP64_TFLOPS,
+           "tor": r.value, "kappa": r.kappa, "err_bound_over_tor": r.err_bound / abs(r.value)}
+    print(f"[bench] n=40 dd: {sec:.2f} s, {out['terms_per_s']:.3e} terms/s, frac {out['frac_fp64_peak']:.3f}",
+          file=sys.stderr, flush=True)
     return out
 
 
@@ -411,8 +461,9 @@ def main():
     ap.add_argument("--mcmc-steps", type=int, default=16)
     ap.add_argument("--mcmc-reps", type=int, default=2)
     ap.add_argument("--no-small", action="store_true", help="skip the n = 16 leg")
-    ap.add_argument("--stress", action="store_true",
-                    help="also run the n = 36 precision-stress leg (about a minute: QD reference)")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the n = 36 precision-stress leg (about 35 s: QD reference)")
+    ap.add_argument("--no-n40", action="store_true", help="skip the n = 40 double-double leg (about 25 s)")
     ap.add_argument("--mcmc-only", action="store_true",
                     help="run only the sampler leg and print its JSON object (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
@@ -511,6 +562,11 @@ def main():
         "algorithmic_flops_all_kernels": (schur_flops(n, args.tier) + (1 << n) * acc_flops(args.tier))
         if algo == "schur" else flops,
     }
+    # forward error of the FP64 value against the DD one (DD's own error is
+    # far below it at this kappa)
+    r64, rdd = (ores, res) if other == "fp64" else (res, ores)
+    line["tiers"]["fp64"]["rel_err_vs_dd"] = float(abs(r64.exact - rdd.exact) / abs(rdd.exact))
+    line["tiers"]["fp64"]["err_vs_dd_over_sabs"] = float(abs(r64.exact - rdd.exact) / rdd.abs_exact)
     if args.batch > 0:
         extra = [float(x) for x in args.batch_taus.split(",") if x.strip()]
         line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check, extra)
@@ -518,8 +574,10 @@ def main():
         line["mcmc"] = mcmc_leg(tor, args.mcmc_chains, args.mcmc_steps, args.mcmc_reps)
     if not args.no_small:
         line["small_n16"] = small_leg(tor)
-    if args.stress:
+    if not args.no_stress:
         line["stress_n36"] = stress_leg(tor)
+    if not args.no_n40:
+        line["n40"] = n40_leg(tor)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(O, n, args.cpu_seconds)

@@ -77,18 +77,21 @@ __device__ __forceinline__ qd r_from_sum<qd>(double a, double b, double c) {
   return prec::qd_add_d(qd{{s, e, 0.0, 0.0}}, c);
 }
 
-// Accumulators of one lane: signed sum and sum of magnitudes (a run of
-// terms, renormalised once by acc_fix).
+// Accumulators of one lane, by the parity of the term's subset size
+// relative to the lane's state (p[0]: even, p[1]: odd).  Every term g =
+// det^(-1/2) is positive, so one run per parity gives both the signed sum
+// (the difference of the two, its sign set by (-1)^(n-|Z|)) and the sum of
+// magnitudes (their sum) with one accumulation per term.
 template <class TT>
 struct LaneAcc {
-  typename TT::Acc t, a;
+  typename TT::Acc p[2];
 };
 
-// Emit the term of a completed subset: (-1)^(n-m) g.
-template <class TT>
-__device__ __forceinline__ void emit_term(LaneAcc<TT>& acc, const typename TT::R& g, int m, int n) {
-  acc.t = TT::acc_run(acc.t, ((n - m) & 1) ? r_neg(g) : g);
-  acc.a = TT::acc_run(acc.a, g);
+// Emit the term g of a completed subset whose size has parity PAR relative
+// to the lane's state.
+template <class TT, int PAR>
+__device__ __forceinline__ void emit_term(LaneAcc<TT>& acc, const typename TT::R& g) {
+  acc.p[PAR] = TT::acc_run(acc.p[PAR], g);
 }
 
 // Pivot of the 2x2 block at rows (2i, 2i+1): reciprocal square roots of the
@@ -150,9 +153,10 @@ template <class TT, int S>
 struct Bottom {
   using R = typename TT::R;
 
-  template <int I>
-  __device__ __forceinline__ static void child(const R (&T)[psize(S)], const R& g, int m, int n,
-                                               LaneAcc<TT>& acc, bool& bad) {
+  // PAR: parity of the state's subset size relative to the lane's state
+  template <int I, int PAR>
+  __device__ __forceinline__ static void child(const R (&T)[psize(S)], const R& g, LaneAcc<TT>& acc,
+                                               bool& bad) {
     constexpr int SC = S - 1 - I;
     constexpr int O = 2 * I + 2;
     if constexpr (SC == 0) {
@@ -160,7 +164,7 @@ struct Bottom {
       const R& p00 = T[pk(2 * I, 2 * I)];
       const R det = r_det2(p00, T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
       if (!(r_lead(p00) > 0.0 && r_lead(det) > 0.0)) bad = true;
-      emit_term(acc, r_mul(g, r_rsqrt(det)), m + 1, n);
+      emit_term<TT, PAR ^ 1>(acc, r_mul(g, r_rsqrt(det)));
     } else {
       const Pivot<R> pv = make_pivot(T[pk(2 * I, 2 * I)], T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
       if (!pv.ok) bad = true;
@@ -179,21 +183,21 @@ struct Bottom {
           C[pk(a, b)] = r_fms2(T[pk(a + O, b + O)], u0[a], u0[b], u1[a], u1[b]);
         }
       }
-      Bottom<TT, SC>::run(C, gc, m + 1, n, acc, bad);
+      Bottom<TT, SC>::template run<PAR ^ 1>(C, gc, acc, bad);
     }
   }
 
-  template <int I>
-  __device__ __forceinline__ static void children(const R (&T)[psize(S)], const R& g, int m, int n,
-                                                  LaneAcc<TT>& acc, bool& bad) {
-    child<I>(T, g, m, n, acc, bad);
-    if constexpr (I > 0) children<I - 1>(T, g, m, n, acc, bad);
+  template <int I, int PAR>
+  __device__ __forceinline__ static void children(const R (&T)[psize(S)], const R& g, LaneAcc<TT>& acc,
+                                                  bool& bad) {
+    child<I, PAR>(T, g, acc, bad);
+    if constexpr (I > 0) children<I - 1, PAR>(T, g, acc, bad);
   }
 
-  __device__ __forceinline__ static void run(const R (&T)[psize(S)], const R& g, int m, int n,
-                                             LaneAcc<TT>& acc, bool& bad) {
-    emit_term(acc, g, m, n);
-    children<S - 1>(T, g, m, n, acc, bad);
+  template <int PAR>
+  __device__ __forceinline__ static void run(const R (&T)[psize(S)], const R& g, LaneAcc<TT>& acc, bool& bad) {
+    emit_term<TT, PAR>(acc, g);
+    children<S - 1, PAR>(T, g, acc, bad);
   }
 };
 
@@ -800,11 +804,15 @@ struct Leaf {
   __device__ __forceinline__ static void finish(const R (&leaf)[psize(SB)], const R& lg, int32_t lm, int L,
                                                 int lane, int n, int z, Acc* partials, bool& bad) {
     LaneAcc<TT> acc;
-    acc.t = TT::acc_zero();
-    acc.a = TT::acc_zero();
-    if (lane < (1 << L)) Bottom<TT, SB>::run(leaf, lg, lm, n, acc, bad);
-    const Acc tt = wave_total<TT>(TT::acc_fix(acc.t));
-    const Acc ta = wave_total<TT>(TT::acc_fix(acc.a));
+    acc.p[0] = TT::acc_zero();
+    acc.p[1] = TT::acc_zero();
+    if (lane < (1 << L)) Bottom<TT, SB>::template run<0>(leaf, lg, acc, bad);
+    // the lane's state has |Z| = lm: its own term has sign (-1)^(n - lm)
+    const Acc pe = TT::acc_fix(acc.p[0]), po = TT::acc_fix(acc.p[1]);
+    const bool odd = ((n - lm) & 1) != 0;
+    const Acc lt = odd ? TT::acc_merge(po, r_neg(pe)) : TT::acc_merge(pe, r_neg(po));
+    const Acc tt = wave_total<TT>(lt);
+    const Acc ta = wave_total<TT>(TT::acc_merge(pe, po));
     if (lane == 0) {
       partials[(size_t)z * 2] = tt;
       partials[(size_t)z * 2 + 1] = ta;
