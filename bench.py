@@ -223,9 +223,16 @@ def batched_leg(tor, count: int, tau: float, steps: int, check: bool, extra_taus
                            "selector": "paper_2009_01177_amd/data/selector_default.txt" if have else None}
     out["gain_learned_vs_fixed_dd"] = s_dd / s_ml
     out["select_ms"] = timed(lambda: tor.tor_select_tiers(b, tau), steps) * 1e3
+    # the learned tiers evaluated on their own (no selection, no spot checks)
+    chosen, _, _ = tor.tor_select_tiers(b, tau)
+    chosen = [int(x) for x in chosen]
+    s_ev = timed(lambda: tor.tor_eval_batched(b, tiers=chosen, graph=True, sync=False), steps)
+    out["auto_learned"]["eval_only_s"] = s_ev
+    out["gain_learned_eval_only_vs_fixed_dd"] = s_dd / s_ev
     out["gain_learned_vs_bounds_only"] = s_fb / s_ml
     print(f"[bench] batched auto: bounds-only {s_fb * 1e3:.1f} ms, learned {s_ml * 1e3:.1f} ms "
-          f"({st_ml})", file=sys.stderr, flush=True)
+          f"({st_ml}); its tiers alone {s_ev * 1e3:.1f} ms, selection {out['select_ms']:.2f} ms",
+          file=sys.stderr, flush=True)
     ref = None
     if check:
         res = tor.tor_eval_batched(b, tau=tau)
@@ -403,7 +410,9 @@ def stress_leg(tor, taus=(1e-3, 1e-6)):
         r = tor.tor_eval_batched(b, tau=tau)[0]
         sec = time.perf_counter() - t
         out["selector"][repr(tau)] = {
-            "tier": ["fp64", "dd", "qd"][int(tiers[0])], "log10_kappa_pred": float(k[0]),
+            "tier": ["fp64", "dd", "qd"][int(tiers[0])],
+            "prediction": float(k[0]), "prediction_is": "log10 of the FP64 tier's forward error (upper quantile)"
+            if tor.tor_selector_get().target == 1 else "log10 kappa",
             "source": "network" if int(src[0]) == 0 else "bound estimate", "s": sec,
             "rel_err_vs_qd": float(abs(r.exact - q.exact) / abs(q.exact))}
         print(f"[bench] n=36 tau={tau:g}: {out['selector'][repr(tau)]}", file=sys.stderr, flush=True)
@@ -454,9 +463,10 @@ def main():
     ap.add_argument("--batch", type=int, default=4096, help="batched leg instances (0: skip)")
     ap.add_argument("--tau", type=float, default=1e-3)
     ap.add_argument("--batch-steps", type=int, default=3)
-    ap.add_argument("--batch-check", action="store_true", help="check the batched leg against QD")
-    ap.add_argument("--batch-taus", default="",
-                    help="further accuracy targets for the batched leg, comma-separated (e.g. 1e-4,1e-6)")
+    ap.add_argument("--no-batch-check", action="store_true",
+                    help="skip checking the batched leg against QD (and timing the ideal tier choice)")
+    ap.add_argument("--batch-taus", default="1e-4,1e-6",
+                    help="further accuracy targets for the batched leg, comma-separated ('' for none)")
     ap.add_argument("--mcmc-chains", type=int, default=1024, help="sampler leg chains (0: skip)")
     ap.add_argument("--mcmc-steps", type=int, default=16)
     ap.add_argument("--mcmc-reps", type=int, default=2)
@@ -498,7 +508,7 @@ def main():
     if args.batch_only:
         extra = [float(x) for x in args.batch_taus.split(",") if x.strip()]
         print(json.dumps({"batched": batched_leg(tor, max(args.batch, 1), args.tau, args.batch_steps,
-                                                 args.batch_check, extra)}), flush=True)
+                                                 not args.no_batch_check, extra)}), flush=True)
         return
 
     n = args.n
@@ -569,7 +579,7 @@ def main():
     line["tiers"]["fp64"]["err_vs_dd_over_sabs"] = float(abs(r64.exact - rdd.exact) / rdd.abs_exact)
     if args.batch > 0:
         extra = [float(x) for x in args.batch_taus.split(",") if x.strip()]
-        line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, args.batch_check, extra)
+        line["batched"] = batched_leg(tor, args.batch, args.tau, args.batch_steps, not args.no_batch_check, extra)
     if args.mcmc_chains > 0:
         line["mcmc"] = mcmc_leg(tor, args.mcmc_chains, args.mcmc_steps, args.mcmc_reps)
     if not args.no_small:

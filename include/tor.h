@@ -280,21 +280,36 @@ int tor_autotune_load(const char* path);
 /* ---- Precision selector (TOR_AUTO) --------------------------------------
  * The paper picks its precision once per run from bounds on the largest and
  * smallest intermediate values (Sec. 5.4, Eq. 5-7).  Here a small network
- * predicts each instance's cancellation ratio kappa = S_abs / |Tor| from
- * cheap features and picks the cheapest tier expected to meet the accuracy
- * target; outside the network's training range the bound estimate decides. */
+ * predicts, from cheap features, either each instance's cancellation ratio
+ * kappa = S_abs / |Tor| or directly an upper quantile of the FP64 tier's
+ * forward error, and the cheapest tier expected to meet the accuracy target
+ * is picked; outside the network's training range the bound estimate
+ * decides. */
 
-#define TOR_NFEAT 12      /* features per instance (see tor_features) */
+#define TOR_NFEAT 20      /* features per instance (see tor_features) */
 #define TOR_MLP_H1 32     /* network: TOR_NFEAT -> 32 -> 32 -> 1, tanh hidden */
 #define TOR_MLP_H2 32
-#define TOR_MLP_PARAMS 1505
+#define TOR_MLP_PARAMS 1761
 
-/* Features of `batch` instances (all n >= 1), binary64, on the device:
- *   f0 n; f1 -1/2 log det(I-O); f2 sum_k log((1+q_k)/(1-q_k)) with
- *   q_k = det(I-O)_{kk}^(1/2); f3 mean_k -log q_k; f4 a = mean Re O_kk;
- *   f5 k = ((1-a)^2 - det(I-O)^(1/n))/n; f6 sum_{i<j} log(det_ij/(det_i det_j));
+/* Features of `batch` instances (all n >= 1), binary64, on the device.
+ * R is the real quadrature form of I - O (same principal minors), Q its
+ * inverse (sigma_Q in the same basis), q_k = det(R_kk)^(1/2):
+ *   f0 n; f1 -1/2 log det R (log of the largest term, the level-n sum
+ *   L_n); f2 sum_k log((1+q_k)/(1-q_k)) (log kappa if the modes were
+ *   independent); f3 mean_k -log q_k; f4 a = mean Re O_kk; f5 Eq. 5's
+ *   k = ((1-a)^2 - det(R)^(1/n))/n; f6 sum_{i<j} log(det_ij/(det_i det_j));
  *   f7 max q_k; f8 min q_k; f9, f10 log of the smallest and largest
- *   Cholesky pivot of I-O in quadrature form; f11 log mean_{i<j} det_ij^(-1/2).
+ *   Cholesky pivot of R; f11 log mean_{i<j} det_ij^(-1/2) (level 2).
+ *   Spectrum of R: f12 the Gershgorin lower bound min_i (R_ii - sum_j!=i
+ *   |R_ij|), f13 log of the Gershgorin upper bound, f14 and f15 log of the
+ *   smallest and largest Ritz value of 12 Lanczos steps (fewer when 2n < 12)
+ *   from the normalised all-ones vector.
+ *   Top levels (their terms over the largest term, t_k = det(Q_kk)^(-1/2)
+ *   for the level-(n-1) subset without mode k, t_kl likewise with the 4x4
+ *   block of modes k, l for level n-2): f16 log mean_k t_k, f17 log max_k
+ *   t_k, f18 log mean_{k<l} t_kl, f19 log max_{k<l} t_kl (0 when n = 1;
+ *   NaN for n > 46, where Q does not fit in LDS beside R: such instances
+ *   are outside any network's range and take the bound estimate).
  * Inputs as tor_eval_batched (offsets, n on the host); feats device,
  * batch x TOR_NFEAT.  Enqueued on `stream`. */
 int tor_features(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
@@ -314,30 +329,101 @@ int tor_mlp_grad(const double* theta, const double* mean, const double* std, con
                  const double* y, int32_t B, double under, double over, void* stream, double* grad,
                  double* loss);
 
+/* Gradient of the mean quantile (pinball) loss at level q in (0, 1),
+ *   L = (1/B) sum_b max(q r_b, (q - 1) r_b),  r_b = y_b - net(x_b),
+ * whose minimiser is the conditional q-quantile of y (an upper quantile of
+ * the error for q near 1).  Arguments as tor_mlp_grad. */
+int tor_mlp_grad_quantile(const double* theta, const double* mean, const double* std, const double* X,
+                          const double* y, int32_t B, double q, void* stream, double* grad,
+                          double* loss);
+
 /* One Adam step (moments m, v, step >= 1) on theta in place; device. */
 int tor_mlp_adam(double* theta, const double* grad, double* m, double* v, double lr, double beta1,
                  double beta2, double eps, int32_t step, void* stream);
 
-/* The selector used by TOR_AUTO (one per process). */
+/* What the network predicts. */
+#define TOR_TARGET_KAPPA 0 /* y = log10 kappa; tier t's predicted error is
+                              log10_c[t] + slope[t] (y + margin) + log10 u_t */
+#define TOR_TARGET_ERR64 1 /* y = an upper quantile of log10 of the FP64 tier's
+                              relative forward error; tier t's predicted error
+                              is y + margin + log10_c[t] */
+
+/* The selector used by TOR_AUTO (one per process).  A tier is chosen when
+ * its predicted error is at most log10 tau; the cheapest such tier wins. */
 typedef struct tor_selector {
   double theta[TOR_MLP_PARAMS];
   double mean[TOR_NFEAT], std[TOR_NFEAT]; /* input standardisation */
   double fmin[TOR_NFEAT], fmax[TOR_NFEAT]; /* training range; outside it the
                                               bound estimate decides */
-  double log10_c[3]; /* per tier t: the error model
-                        log10(|dTor|/|Tor|) <= log10_c[t] + slope[t] (log10 kappa
-                        + margin) + log10 u_t, both calibrated on training data */
-  double slope[3];   /* per tier, in (0, 2]; 1: error proportional to kappa */
+  double log10_c[3]; /* per tier: the error model's offset (see target) */
+  double slope[3];   /* per tier, in (0, 2]; TOR_TARGET_KAPPA only */
   double margin;     /* extra log10 safety margin on the prediction */
   int32_t nmin, nmax; /* training range of n */
   int32_t trained;    /* 0: no network, the bound estimate decides */
-  int32_t reserved;
+  int32_t target;     /* TOR_TARGET_KAPPA or TOR_TARGET_ERR64 */
 } tor_selector_t;
 
 int tor_selector_set(const tor_selector_t* sel); /* NULL clears it */
 int tor_selector_get(tor_selector_t* sel);
 int tor_selector_save(const char* path);
 int tor_selector_load(const char* path);
+
+/* ---- Selector training (Sec. 5.4's precision choice, learned) ----------- */
+
+/* Labels of `count` instances from the library's own evaluations: the
+ * reference tier (TOR_QD, or TOR_DD where QD would be slow) gives Tor and
+ * S_abs, and the cheaper tiers are evaluated beside it.
+ *   O_packed, offsets, n  as tor_eval_batched (offsets, n host)
+ *   ref_tier   TOR_QD or TOR_DD
+ *   labels     host, count x 4: [0] log10 kappa = log10(S_abs / |Tor|)
+ *              (60 when Tor is exactly 0); [1], [2] log10 of the FP64 and DD
+ *              values' relative forward errors |T_t - T_ref| / |T_ref| (at
+ *              least log10 u_t - 2; the DD one NaN when DD is the
+ *              reference); [3] NaN.  NaN rows for n = 0 or a failed
+ *              reference.
+ * Synchronous; allocates a result buffer for the call. */
+int tor_selector_label(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t count,
+                       int32_t ref_tier, void* stream, double* labels);
+
+#define TOR_LOSS_ASYM_SQUARED 0 /* tor_mlp_grad's loss (under, over) */
+#define TOR_LOSS_QUANTILE 1     /* tor_mlp_grad_quantile's loss (quantile) */
+
+typedef struct tor_train_options {
+  int32_t target;     /* TOR_TARGET_KAPPA or TOR_TARGET_ERR64 */
+  int32_t loss;       /* TOR_LOSS_ASYM_SQUARED or TOR_LOSS_QUANTILE */
+  int32_t epochs;     /* passes over the samples */
+  int32_t batch_size; /* samples per Adam step */
+  double lr, beta1, beta2, eps; /* Adam */
+  double under, over; /* asymmetric squared loss weights */
+  double quantile;    /* quantile loss level */
+  double slack;       /* decades added to each tier's calibrated offset */
+  double margin;      /* tor_selector_t.margin of the result */
+  uint64_t seed;      /* initial weights and sample order */
+} tor_train_options_t;
+
+/* Train the selector network on the GPU by the library's kernels
+ * (tor_mlp_grad / tor_mlp_grad_quantile per minibatch, fixed-order sums,
+ * tor_mlp_adam) and calibrate its per-tier error model on the training
+ * samples (Sec. 5.4's choice of precision from an error estimate).
+ *   feats   host, count x TOR_NFEAT (tor_features)
+ *   labels  host, count x 4 (tor_selector_label); rows whose target or
+ *           features are not finite are skipped
+ *   n       host, count
+ *   opt     options (all fields used)
+ *   out     host: the trained selector (not installed: tor_selector_set)
+ *   losses  host, opt->epochs mean losses, or NULL
+ * Weights start normal with standard deviation 1/sqrt(fan in) from a
+ * splitmix64 stream of opt->seed, biases at 0; every epoch visits the samples
+ * in a new order from the same stream.  Calibration, per tier t in {FP64, DD}
+ * over the samples where its error is measured: TOR_TARGET_ERR64: log10_c[t]
+ * = max (log10 err_t - y_pred) + slack; TOR_TARGET_KAPPA: for each slope in
+ * [0.3, 1] the intercept is the upper envelope of log10(err_t / u_t) - s
+ * log10 kappa, and the slope whose envelope is lowest on average is kept
+ * (+ slack).  QD takes DD's model scaled by their unit roundoffs.  The same
+ * inputs and options give the same selector bit for bit.  Synchronous;
+ * allocates device memory for the call. */
+int tor_selector_train(const double* feats, const double* labels, const int32_t* n, int32_t count,
+                       const tor_train_options_t* opt, void* stream, tor_selector_t* out, double* losses);
 
 /* Bound-based estimate of the significand bits an instance needs (Eq. 7 read
  * for floating tiers): log2 of the rigorous S_abs <= 2^n det(I-O)^(-1/2) over

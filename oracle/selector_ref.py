@@ -30,7 +30,8 @@ import math
 
 import numpy as np
 
-NFEAT = 12
+NFEAT = 20
+LANCZOS_STEPS = 12
 
 
 def real_form(O):
@@ -55,8 +56,33 @@ def _mode_idx(modes):
     return [r for k in modes for r in (2 * k, 2 * k + 1)]
 
 
+def lanczos_ritz_extremes(R, steps=LANCZOS_STEPS):
+    """Smallest and largest Ritz value of `steps` Lanczos steps on the
+    symmetric R from the normalised all-ones vector (the textbook three-term
+    recurrence, no reorthogonalisation; stops early on an invariant
+    subspace); the tridiagonal's eigenvalues by LAPACK."""
+    N = R.shape[0]
+    k = min(N, steps)
+    v_prev = np.zeros(N)
+    v = np.ones(N) / math.sqrt(N)
+    al, be = [], []
+    for j in range(k):
+        w = R @ v
+        a = float(w @ v)
+        w = w - a * v - (be[-1] if be else 0.0) * v_prev
+        b = float(np.linalg.norm(w))
+        al.append(a)
+        be.append(b)
+        if not b > 1e-12 * abs(a):
+            break
+        v_prev, v = v, w / b
+    T = np.diag(al) + np.diag(be[:len(al) - 1], 1) + np.diag(be[:len(al) - 1], -1)
+    ev = np.linalg.eigvalsh(T)
+    return float(ev[0]), float(ev[-1])
+
+
 def features(O) -> np.ndarray:
-    """The selector's 12 features of one instance (n >= 1)."""
+    """The selector's 20 features of one instance (n >= 1)."""
     O = np.asarray(O, dtype=np.complex128)
     n = O.shape[0] // 2
     R = real_form(O)
@@ -90,6 +116,23 @@ def features(O) -> np.ndarray:
     f[9] = float(np.log(np.min(piv)))
     f[10] = float(np.log(np.max(piv)))
     f[11] = float(math.log(np.mean(pair_terms))) if pair_terms else 0.0
+    # spectrum of R: Gershgorin discs and Lanczos Ritz values
+    off = np.sum(np.abs(R), axis=1) - np.abs(np.diag(R))
+    f[12] = float(np.min(np.diag(R) - off))
+    f[13] = float(math.log(np.max(np.diag(R) + off)))
+    lo, hi = lanczos_ritz_extremes(R)
+    f[14] = math.log(lo)
+    f[15] = math.log(hi)
+    # top levels: det R_{-Z} / det R = det Q_Z for Q = R^-1 (Jacobi), so a
+    # level-(n - |Z|) term over the largest term is det(Q_Z)^(-1/2)
+    Q = np.linalg.inv(R)
+    t1 = [np.linalg.det(Q[np.ix_(_mode_idx([k]), _mode_idx([k]))]) ** -0.5 for k in range(n)]
+    t2 = [np.linalg.det(Q[np.ix_(_mode_idx([i, j]), _mode_idx([i, j]))]) ** -0.5
+          for i in range(n) for j in range(i + 1, n)]
+    f[16] = math.log(np.mean(t1))
+    f[17] = math.log(np.max(t1))
+    f[18] = math.log(np.mean(t2)) if t2 else 0.0
+    f[19] = math.log(np.max(t2)) if t2 else 0.0
     return f
 
 
@@ -112,7 +155,7 @@ def fallback_bits(O, tau: float, alpha: float = 0.5) -> float:
     return b_cancel + b_sgn + b_accum
 
 
-# ---- network: 12 -> 32 -> 32 -> 1, tanh hidden layers ----------------------
+# ---- network: 20 -> 32 -> 32 -> 1, tanh hidden layers ----------------------
 
 SIZES = (NFEAT, 32, 32, 1)
 
@@ -151,8 +194,14 @@ def loss_weights(err, under: float, over: float):
     return np.where(err > 0, under, over)
 
 
-def mlp_loss_and_grad(theta, X, y, mean, std, under=4.0, over=1.0):
-    """Mean asymmetric squared loss and its exact gradient w.r.t. theta."""
+def pinball(r, q: float):
+    """Quantile loss of residuals r = y - prediction at level q."""
+    return np.where(r > 0, q * r, (q - 1.0) * r)
+
+
+def mlp_loss_and_grad(theta, X, y, mean, std, under=4.0, over=1.0, quantile=None):
+    """Mean loss and its exact gradient w.r.t. theta: the asymmetric squared
+    loss (under, over), or with `quantile` = q the pinball loss at level q."""
     theta = np.asarray(theta, dtype=np.float64)
     layers = unpack(theta)
     B = X.shape[0]
@@ -166,10 +215,15 @@ def mlp_loss_and_grad(theta, X, y, mean, std, under=4.0, over=1.0):
         acts.append(h)
     pred = acts[-1][:, 0]
     err = y - pred
-    w = loss_weights(err, under, over)
-    loss = float(np.mean(w * err * err))
-    # dL/dpred = -2 w err / B
-    delta = (-2.0 * w * err / B)[:, None]
+    if quantile is None:
+        w = loss_weights(err, under, over)
+        loss = float(np.mean(w * err * err))
+        # dL/dpred = -2 w err / B
+        delta = (-2.0 * w * err / B)[:, None]
+    else:
+        loss = float(np.mean(pinball(err, quantile)))
+        # dL/dpred = -q / B above the prediction, (1 - q) / B below
+        delta = (np.where(err > 0, -quantile, 1.0 - quantile) / B)[:, None]
     grads = []
     for li in range(len(layers) - 1, -1, -1):
         W, b = layers[li]

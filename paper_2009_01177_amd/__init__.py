@@ -12,5 +12,6 @@ from .api import (  # noqa: F401
     tor_selector_save, tor_selector_load, tor_fallback_bits, tor_select_tiers, tor_last_select_stats,
     tor_autotune, tor_autotune_save, tor_autotune_load, tor_mcmc, results_of, tier_id,
     tor_eval_part, tor_combine_parts, tor_workspace_bytes,
-    tor_batch_workspace_bytes, tor_eval_noalloc, tor_noalloc_nmax,
+    tor_batch_workspace_bytes, tor_eval_noalloc, tor_noalloc_nmax, tor_mlp_grad_quantile,
+    tor_selector_label, tor_selector_train, train_options,
 )

@@ -31,10 +31,13 @@ EXPORTS = (
     "tor_fallback_bits", "tor_select_tiers", "tor_last_select_stats",
     "tor_autotune", "tor_autotune_save", "tor_autotune_load", "tor_workspace_bytes",
     "tor_batch_workspace_bytes", "tor_eval_noalloc", "tor_noalloc_nmax",
+    "tor_mlp_grad_quantile", "tor_selector_label", "tor_selector_train",
 )
 
-TOR_NFEAT = 12
-TOR_MLP_PARAMS = 1505
+TOR_NFEAT = 20
+TOR_MLP_PARAMS = 1761
+TOR_TARGET_KAPPA, TOR_TARGET_ERR64 = 0, 1
+TOR_LOSS_ASYM_SQUARED, TOR_LOSS_QUANTILE = 0, 1
 
 
 class TorResultC(ctypes.Structure):
@@ -60,18 +63,37 @@ class TorOptionsC(ctypes.Structure):
 
 class TorSelectorC(ctypes.Structure):
     _fields_ = [
-        ("theta", ctypes.c_double * 1505),
-        ("mean", ctypes.c_double * 12),
-        ("std", ctypes.c_double * 12),
-        ("fmin", ctypes.c_double * 12),
-        ("fmax", ctypes.c_double * 12),
+        ("theta", ctypes.c_double * TOR_MLP_PARAMS),
+        ("mean", ctypes.c_double * TOR_NFEAT),
+        ("std", ctypes.c_double * TOR_NFEAT),
+        ("fmin", ctypes.c_double * TOR_NFEAT),
+        ("fmax", ctypes.c_double * TOR_NFEAT),
         ("log10_c", ctypes.c_double * 3),
         ("slope", ctypes.c_double * 3),
         ("margin", ctypes.c_double),
         ("nmin", ctypes.c_int32),
         ("nmax", ctypes.c_int32),
         ("trained", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("target", ctypes.c_int32),
+    ]
+
+
+class TorTrainOptionsC(ctypes.Structure):
+    _fields_ = [
+        ("target", ctypes.c_int32),
+        ("loss", ctypes.c_int32),
+        ("epochs", ctypes.c_int32),
+        ("batch_size", ctypes.c_int32),
+        ("lr", ctypes.c_double),
+        ("beta1", ctypes.c_double),
+        ("beta2", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("under", ctypes.c_double),
+        ("over", ctypes.c_double),
+        ("quantile", ctypes.c_double),
+        ("slack", ctypes.c_double),
+        ("margin", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
     ]
 
 
@@ -158,6 +180,15 @@ def lib():
     L.tor_mlp_forward.argtypes = [vp, vp, vp, vp, i32, vp, vp]
     L.tor_mlp_grad.restype = ctypes.c_int
     L.tor_mlp_grad.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    L.tor_mlp_grad_quantile.restype = ctypes.c_int
+    L.tor_mlp_grad_quantile.argtypes = [vp, vp, vp, vp, vp, i32, ctypes.c_double, vp, vp, vp]
+    L.tor_selector_label.restype = ctypes.c_int
+    L.tor_selector_label.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32), i32, i32,
+                                     vp, ctypes.POINTER(ctypes.c_double)]
+    L.tor_selector_train.restype = ctypes.c_int
+    L.tor_selector_train.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int32), i32, ctypes.POINTER(TorTrainOptionsC), vp,
+                                     ctypes.POINTER(TorSelectorC), ctypes.POINTER(ctypes.c_double)]
     L.tor_mlp_adam.restype = ctypes.c_int
     L.tor_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, i32, vp]

@@ -264,7 +264,7 @@ def _dptr_t(t):
 
 
 def tor_features(batch: "Batch", stream=None):
-    """(B, 12) float64 device tensor of the instances' selector features."""
+    """(B, TOR_NFEAT) float64 device tensor of the instances' selector features."""
     torch = _torch()
     f = torch.zeros((batch.batch, _lib.TOR_NFEAT), dtype=torch.float64, device=batch.O.device)
     rc = lib().tor_features(_dptr_t(batch.O),
@@ -292,6 +292,60 @@ def tor_mlp_grad(theta, mean, std, X, y, under=4.0, over=1.0, stream=None):
                              X.shape[0], float(under), float(over), _stream_ptr(stream), _dptr_t(grad),
                              _dptr_t(loss)), "tor_mlp_grad")
     return grad, loss
+
+
+def tor_mlp_grad_quantile(theta, mean, std, X, y, q=0.9, stream=None):
+    """(grad, loss) device tensors of the quantile loss at level q."""
+    torch = _torch()
+    grad = torch.zeros(_lib.TOR_MLP_PARAMS, dtype=torch.float64, device=X.device)
+    loss = torch.zeros(1, dtype=torch.float64, device=X.device)
+    check(lib().tor_mlp_grad_quantile(_dptr_t(theta), _dptr_t(mean), _dptr_t(std), _dptr_t(X), _dptr_t(y),
+                                      X.shape[0], float(q), _stream_ptr(stream), _dptr_t(grad), _dptr_t(loss)),
+          "tor_mlp_grad_quantile")
+    return grad, loss
+
+
+def tor_selector_label(batch: "Batch", ref_tier="qd", stream=None) -> np.ndarray:
+    """(B, 4) host array of labels: log10 kappa and log10 of the FP64 and DD
+    relative forward errors against the reference tier (include/tor.h)."""
+    out = np.full((batch.batch, 4), np.nan, dtype=np.float64)
+    check(lib().tor_selector_label(_dptr_t(batch.O), batch.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   batch.n.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), batch.batch,
+                                   tier_id(ref_tier), _stream_ptr(stream),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "tor_selector_label")
+    return out
+
+
+def train_options(target="err64", loss="quantile", epochs=400, batch_size=512, lr=3e-3, beta1=0.9,
+                  beta2=0.999, eps=1e-8, under=4.0, over=1.0, quantile=0.9, slack=0.3, margin=0.0,
+                  seed=0) -> "_lib.TorTrainOptionsC":
+    o = _lib.TorTrainOptionsC()
+    o.target = {"kappa": _lib.TOR_TARGET_KAPPA, "err64": _lib.TOR_TARGET_ERR64}[target]
+    o.loss = {"asym_squared": _lib.TOR_LOSS_ASYM_SQUARED, "quantile": _lib.TOR_LOSS_QUANTILE}[loss]
+    o.epochs, o.batch_size = int(epochs), int(batch_size)
+    o.lr, o.beta1, o.beta2, o.eps = float(lr), float(beta1), float(beta2), float(eps)
+    o.under, o.over, o.quantile = float(under), float(over), float(quantile)
+    o.slack, o.margin, o.seed = float(slack), float(margin), int(seed)
+    return o
+
+
+def tor_selector_train(feats, labels, n, opt: "_lib.TorTrainOptionsC", stream=None):
+    """Train and calibrate a selector (include/tor.h); returns (TorSelectorC,
+    per-epoch mean losses).  feats (B, TOR_NFEAT), labels (B, 4), n (B,):
+    host arrays; the selector is not installed."""
+    X = np.ascontiguousarray(feats, dtype=np.float64)
+    L = np.ascontiguousarray(labels, dtype=np.float64)
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    if X.ndim != 2 or X.shape[1] != _lib.TOR_NFEAT or L.shape != (X.shape[0], 4) or nn.shape != (X.shape[0],):
+        raise ValueError("feats (B, TOR_NFEAT), labels (B, 4) and n (B,) expected")
+    sel = _lib.TorSelectorC()
+    losses = np.zeros(opt.epochs, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    check(lib().tor_selector_train(X.ctypes.data_as(dp), L.ctypes.data_as(dp),
+                                   nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), X.shape[0],
+                                   ctypes.byref(opt), _stream_ptr(stream), ctypes.byref(sel),
+                                   losses.ctypes.data_as(dp)), "tor_selector_train")
+    return sel, losses
 
 
 def tor_mlp_adam(theta, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

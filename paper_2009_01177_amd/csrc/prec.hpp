@@ -301,6 +301,34 @@ PREC_HD qd qd_add(qd a, qd b) {
 
 PREC_HD qd qd_sub(qd a, qd b) { return qd_add(a, qd_neg(b)); }
 
+// The words of a quad-double rewritten as a non-overlapping expansion with
+// the same exact sum, largest first (zeros last): each word lies below the
+// lowest set bit of the one before.  The arithmetic above keeps sums exact
+// but, after heavy cancellation, may leave overlapping words; an output
+// value is put in this form so that its leading word is within an ulp of
+// the sum.  Shewchuk's Grow-Expansion ("Adaptive precision
+// floating-point arithmetic", 1997): adding a double to a non-overlapping
+// expansion by a chain of two_sums gives a non-overlapping expansion of the
+// exact sum, components in increasing magnitude.
+PREC_HD qd qd_nonoverlapping(qd a) {
+  double e[4] = {a.x[3], 0.0, 0.0, 0.0};
+  int m = 1;
+  for (int k = 2; k >= 0; --k) {
+    double q = a.x[k];
+    for (int i = 0; i < m; ++i) {
+      double h;
+      two_sum(q, e[i], q, h);
+      e[i] = h;
+    }
+    e[m++] = q;
+  }
+  qd z{{0.0, 0.0, 0.0, 0.0}};
+  int j = 0;
+  for (int i = 3; i >= 0; --i)
+    if (e[i] != 0.0) z.x[j++] = e[i];
+  return z;
+}
+
 PREC_HD qd qd_add_d(qd a, double b) {
   double t[5] = {a.x[0], b, a.x[1], a.x[2], a.x[3]};
   return qd_compress<5>(t);

@@ -808,6 +808,13 @@ double tier_unit_log10(int t) {
 
 // Bound estimate of the significand bits an instance needs (Eq. 7 for
 // floating tiers; see the declaration in tor.h).  feats as tor_features.
+// log10 of the relative forward error the selector expects of tier t for
+// an instance whose network output is y.
+double predicted_log10_err(const tor_selector_t& sel, int t, double y) {
+  if (sel.target == TOR_TARGET_ERR64) return y + sel.margin + sel.log10_c[t];
+  return sel.log10_c[t] + sel.slope[t] * (y + sel.margin) + tier_unit_log10(t);
+}
+
 double fallback_bits(const double* f, double tau) {
   const double n = f[0];
   const double logdet = -2.0 * f[1];
@@ -901,7 +908,7 @@ int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, con
       } else {
         t = TOR_QD;
         for (int c = TOR_FP64; c <= TOR_DD; ++c) {
-          if (sel.log10_c[c] + sel.slope[c] * (hp[i] + sel.margin) + tier_unit_log10(c) <= ltau) {
+          if (predicted_log10_err(sel, c, hp[i]) <= ltau) {
             t = c;
             break;
           }
@@ -928,7 +935,7 @@ int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, con
 int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
                int batch, const int32_t* tiers_req, double tau, std::vector<int32_t>& tier_of,
                const std::vector<double>& pred, const std::vector<int32_t>& src, tor_result_t* out,
-               hipStream_t s) {
+               bool use_graph, hipStream_t s) {
   double frac = 1.0 / 32.0;
   if (const char* e = getenv("TOR_SPOT_FRACTION")) {
     const double v = atof(e);
@@ -952,7 +959,7 @@ int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const
     for (int k = 0; k < batch; ++k) {
       if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t) {
         cls.push_back(k);
-        const double lerr = sel.log10_c[t] + sel.slope[t] * (pred[k] + sel.margin) + tier_unit_log10(t);
+        const double lerr = predicted_log10_err(sel, t, pred[k]);
         if (src[k] == 0 && lerr >= ltau - window) near.push_back(k);
       }
     }
@@ -966,7 +973,12 @@ int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const
     tor_result_t* scratch = (tor_result_t*)w->aux;
     std::vector<int32_t> up(tier_of);
     for (int32_t k : sample) up[k] = t + 1;
-    TOR_TRY(batch_core(w, O_packed, offsets, n, sample, up, nullptr, scratch, false, s));
+    // the sample's evaluation is one more batch, replayed from the graph
+    // cache when the same batch comes again
+    tor_options_t gopt;
+    memset(&gopt, 0, sizeof(gopt));
+    gopt.flags = TOR_FLAG_GRAPH;
+    TOR_TRY(batch_core(w, O_packed, offsets, n, sample, up, use_graph ? &gopt : nullptr, scratch, use_graph, s));
     std::vector<tor_result_t> hi(batch), lo(batch);
     TOR_HIP(hipMemcpyAsync(hi.data(), scratch, rbytes, hipMemcpyDeviceToHost, s));
     TOR_HIP(hipMemcpyAsync(lo.data(), out, rbytes, hipMemcpyDeviceToHost, s));
@@ -1225,7 +1237,8 @@ int tor_combine_parts(int32_t tier, int32_t n, const tor_result_t* parts, int32_
   }
   memset(out, 0, sizeof(*out));
   if (tier == TOR_QD) {
-    for (int i = 0; i < 4; ++i) out->tor[i] = t4.x[i];
+    const prec::qd z = prec::qd_nonoverlapping(t4);
+    for (int i = 0; i < 4; ++i) out->tor[i] = z.x[i];
   } else {
     out->tor[0] = t2.hi;
     out->tor[1] = t2.lo;
@@ -1268,7 +1281,8 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   std::vector<int32_t> all(batch);
   for (int k = 0; k < batch; ++k) all[k] = k;
   TOR_TRY(batch_core(w, O_packed, offsets, n, all, tier_of, opt, out, use_graph, s));
-  if (any_auto) TOR_TRY(spot_check(w, O_packed, offsets, n, batch, tiers, tau, tier_of, pred, src, out, s));
+  if (any_auto)
+    TOR_TRY(spot_check(w, O_packed, offsets, n, batch, tiers, tau, tier_of, pred, src, out, use_graph, s));
   return TOR_OK;
 }
 
@@ -1456,8 +1470,9 @@ int tor_selector_set(const tor_selector_t* sel) {
       for (int i = 0; i < TOR_NFEAT; ++i)
         if (!(sel->std[i] > 0.0)) return TOR_EINVAL;
       if (sel->nmin < 1 || sel->nmax < sel->nmin || sel->nmax > TOR_NMAX) return TOR_EINVAL;
+      if (sel->target != TOR_TARGET_KAPPA && sel->target != TOR_TARGET_ERR64) return TOR_EINVAL;
       for (int t = 0; t < 3; ++t)
-        if (!(sel->slope[t] > 0.0 && sel->slope[t] <= 2.0)) return TOR_EINVAL;
+        if (sel->target == TOR_TARGET_KAPPA && !(sel->slope[t] > 0.0 && sel->slope[t] <= 2.0)) return TOR_EINVAL;
     }
     g_sel = *sel;
   } else {
@@ -1485,7 +1500,7 @@ int tor_selector_save(const char* path) {
     for (int i = 0; i < cnt; ++i) fprintf(f, " %.17g", v[i]);
     fprintf(f, "\n");
   };
-  fprintf(f, "tor_selector 2\n");
+  fprintf(f, "tor_selector 3\n");
   arr("theta", sel.theta, TOR_MLP_PARAMS);
   arr("mean", sel.mean, TOR_NFEAT);
   arr("std", sel.std, TOR_NFEAT);
@@ -1494,7 +1509,7 @@ int tor_selector_save(const char* path) {
   arr("log10_c", sel.log10_c, 3);
   arr("slope", sel.slope, 3);
   arr("margin", &sel.margin, 1);
-  fprintf(f, "nrange %d %d\ntrained %d\n", sel.nmin, sel.nmax, sel.trained);
+  fprintf(f, "nrange %d %d\ntrained %d\ntarget %d\n", sel.nmin, sel.nmax, sel.trained, sel.target);
   const int ok = fclose(f) == 0;
   return ok ? TOR_OK : TOR_EINVAL;
 }
@@ -1507,10 +1522,9 @@ int tor_selector_load(const char* path) {
   memset(&sel, 0, sizeof(sel));
   char name[64];
   int version = 0, rc = TOR_OK;
-  // version 1 files predate the slope: their error model is proportional
-  // to kappa (slope 1)
-  if (fscanf(f, "%63s %d", name, &version) != 2 || strcmp(name, "tor_selector") != 0 ||
-      (version != 1 && version != 2))
+  // version 3: TOR_NFEAT = 20 features and the network's target; older
+  // files hold networks of 12 features and are refused
+  if (fscanf(f, "%63s %d", name, &version) != 2 || strcmp(name, "tor_selector") != 0 || version != 3)
     rc = TOR_EINVAL;
   auto arr = [&](const char* want, double* v, int cnt) {
     int c = 0;
@@ -1528,14 +1542,11 @@ int tor_selector_load(const char* path) {
   arr("fmin", sel.fmin, TOR_NFEAT);
   arr("fmax", sel.fmax, TOR_NFEAT);
   arr("log10_c", sel.log10_c, 3);
-  if (version >= 2) {
-    arr("slope", sel.slope, 3);
-  } else {
-    for (int t = 0; t < 3; ++t) sel.slope[t] = 1.0;
-  }
+  arr("slope", sel.slope, 3);
   arr("margin", &sel.margin, 1);
   if (rc == TOR_OK && fscanf(f, "%63s %d %d", name, &sel.nmin, &sel.nmax) != 3) rc = TOR_EINVAL;
   if (rc == TOR_OK && fscanf(f, "%63s %d", name, &sel.trained) != 2) rc = TOR_EINVAL;
+  if (rc == TOR_OK && fscanf(f, "%63s %d", name, &sel.target) != 2) rc = TOR_EINVAL;
   fclose(f);
   if (rc != TOR_OK) return rc;
   return tor_selector_set(&sel);
@@ -1584,7 +1595,21 @@ int tor_mlp_grad(const double* theta, const double* mean, const double* std, con
   TOR_TRY(ensure_aux(w, need, s));
   double* G = (double*)w->aux;
   double* lossb = G + (size_t)B * TOR_MLP_PARAMS;
-  TOR_HIP(launch_mlp_grad(theta, mean, std, X, y, B, under, over, G, lossb, grad, loss, s));
+  TOR_HIP(launch_mlp_grad(theta, mean, std, X, y, B, 0, under, over, G, lossb, grad, loss, s));
+  return TOR_OK;
+}
+
+int tor_mlp_grad_quantile(const double* theta, const double* mean, const double* std, const double* X,
+                          const double* y, int32_t B, double q, void* stream, double* grad, double* loss) {
+  if (B <= 0 || !theta || !mean || !std || !X || !y || !grad || !(q > 0.0 && q < 1.0)) return TOR_EINVAL;
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  const size_t need = sizeof(double) * ((size_t)B * TOR_MLP_PARAMS + B);
+  TOR_TRY(ensure_aux(w, need, s));
+  double* G = (double*)w->aux;
+  double* lossb = G + (size_t)B * TOR_MLP_PARAMS;
+  TOR_HIP(launch_mlp_grad(theta, mean, std, X, y, B, 1, q, 0.0, G, lossb, grad, loss, s));
   return TOR_OK;
 }
 
@@ -1616,8 +1641,12 @@ int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, voi
   TOR_HIP(hipStreamSynchronize(s));
   *out = *w->host_res;
   const int per = (int)(ab / sizeof(double));
-  for (int m = 0; m <= n; ++m)
-    for (int k = 0; k < 4; ++k) out_levels[4 * m + k] = k < per ? w->host_lev[per * m + k] : 0.0;
+  for (int m = 0; m <= n; ++m) {
+    prec::qd v{{0.0, 0.0, 0.0, 0.0}};
+    for (int k = 0; k < per && k < 4; ++k) v.x[k] = w->host_lev[per * m + k];
+    if (per == 4) v = prec::qd_nonoverlapping(v);
+    for (int k = 0; k < 4; ++k) out_levels[4 * m + k] = v.x[k];
+  }
   return out->status;
 }
 

@@ -340,15 +340,17 @@ __device__ inline void acc_store(const dd& a, double* out4) {
   out4[3] = 0.0;
 }
 __device__ inline void acc_store(const qd& a, double* out4) {
-  for (int i = 0; i < 4; ++i) out4[i] = a.x[i];
+  const qd z = prec::qd_nonoverlapping(a);
+  for (int i = 0; i < 4; ++i) out4[i] = z.x[i];
 }
 __device__ inline void acc_store2(const dd& a, double* out2) {
   out2[0] = a.hi;
   out2[1] = a.lo;
 }
 __device__ inline void acc_store2(const qd& a, double* out2) {
+  const qd z = prec::qd_nonoverlapping(a);
   double s, e;
-  prec::fast_two_sum(a.x[0], a.x[1] + (a.x[2] + a.x[3]), s, e);
+  prec::fast_two_sum(z.x[0], z.x[1] + (z.x[2] + z.x[3]), s, e);
   out2[0] = s;
   out2[1] = e;
 }

@@ -103,9 +103,14 @@ hipError_t launch_features(const double2* O, const int64_t* offs, const int32_t*
                            int nmax, double* feats, hipStream_t s);
 hipError_t launch_mlp_forward(const double* th, const double* mean, const double* sd,
                               const double* X, int B, double* Y, hipStream_t s);
+// kind 0: asymmetric squared loss (under, over); kind 1: quantile loss at
+// level q = under.  G: B x TOR_MLP_PARAMS scratch, lossb: B scratch.
 hipError_t launch_mlp_grad(const double* th, const double* mean, const double* sd, const double* X,
-                           const double* y, int B, double under, double over, double* G,
+                           const double* y, int B, int kind, double under, double over, double* G,
                            double* lossb, double* grad, double* loss, hipStream_t s);
+// Minibatch rows idx[0..B) of X (TOR_NFEAT columns) and y into Xo, yo.
+hipError_t launch_gather_samples(const double* X, const double* y, const int32_t* idx, int B, double* Xo,
+                                 double* yo, hipStream_t s);
 hipError_t launch_adam(double* th, const double* grad, double* m, double* v, double lr, double b1,
                        double b2, double eps, int step, hipStream_t s);
 

@@ -1,30 +1,42 @@
 """Training the learned precision selector on the GPU.
 
-The selector predicts y = log10(S_abs / |Tor|), the cancellation ratio that
-decides how many of a tier's bits survive the alternating sum (Sec. 5.1),
-from the 12 features of tor_features.  Labels come from the library's own
-quad-double evaluations, and for larger n (where quad-double is slow) from
-double-double ones, which resolve kappa far below their 1e25 or so; the
-per-tier error model |dTor|/|Tor| <= C_t kappa^s_t u_t is calibrated from
-FP64 and double-double evaluations of the same instances (FP64 against the
-reference tier; double-double only where quad-double is the reference).  Forward passes, gradients and Adam steps
-run in the library's HIP kernels (tor_mlp_forward / tor_mlp_grad /
-tor_mlp_adam); this module only drives them.
+The network reads the TOR_NFEAT features of tor_features and predicts an
+upper quantile of log10 of the FP64 tier's relative forward error (or, for
+TOR_TARGET_KAPPA, log10 of the cancellation ratio S_abs / |Tor| that decides
+how many of a tier's bits survive the alternating sum, Sec. 5.1).  Labels,
+training and calibration run inside the library (tor_selector_label,
+tor_selector_train: the library's evaluations, its gradient and Adam
+kernels, its calibration); this module generates the training instances and
+marshals arguments.
 """
 from __future__ import annotations
 
 import math
 import os
-from dataclasses import dataclass
 
 import numpy as np
 
-from . import _lib
-from .api import (Batch, tor_eval_batched, tor_features, tor_mlp_adam, tor_mlp_forward, tor_mlp_grad,
-                  tor_selector_set)
+from .api import Batch, tor_features, tor_selector_label, tor_selector_set, tor_selector_train, train_options
 
-U = {0: 2.0 ** -53, 1: 2.0 ** -104, 2: 2.0 ** -208}
-YMAX = 60.0  # cap of log10 kappa (Tor == 0 exactly gives kappa = inf)
+
+def family_instances(states: int, per: int, seed: int, nlo: int, nhi: int, M: int = 100,
+                     r=(0.8, 1.6), eta: float = 0.3):
+    """Click patterns of `states` lossy GBS states of one family (Haar U on
+    M modes, squeezing r ~ U[r], transmission eta), each state from its own
+    seed (seed, seed + 1, ...), `per` patterns each with n ~ U{nlo..nhi}
+    modes chosen uniformly."""
+    import gbs_inputs as g
+    out = []
+    for k in range(states):
+        rng = np.random.Generator(np.random.PCG64(seed + k))
+        U = g.haar_unitary(M, rng)
+        rr = rng.uniform(r[0], r[1], size=M)
+        Of = g.o_from_sigma_q(g.gbs_sigma_q(U, rr, eta))
+        prng = np.random.Generator(np.random.PCG64(seed + k + 77777))
+        for _ in range(per):
+            n = int(prng.integers(nlo, nhi + 1))
+            out.append(g.click_submatrix(Of, np.sort(prng.choice(M, size=n, replace=False))))
+    return out
 
 
 def training_instances(count: int, nlo: int, nhi: int, seed: int, M: int = 60):
@@ -51,168 +63,65 @@ def training_instances(count: int, nlo: int, nhi: int, seed: int, M: int = 60):
     return out
 
 
-@dataclass
-class Labels:
-    X: np.ndarray        # (B, 12) features
-    y: np.ndarray        # log10 kappa from the reference tier
-    err: dict            # tier -> relative forward error |T_t - T_ref| / |T_ref| (nan: no reference)
-    n: np.ndarray
-
-    def __add__(self, o: "Labels") -> "Labels":
-        return Labels(np.concatenate([self.X, o.X]), np.concatenate([self.y, o.y]),
-                      {t: np.concatenate([self.err[t], o.err[t]]) for t in self.err},
-                      np.concatenate([self.n, o.n]))
-
-
-def label(Os, chunk: int = 1024, ref: str = "qd") -> Labels:
-    """Features and labels of instances, all on the GPU.  ref: the tier whose
-    value and S_abs give kappa, "qd" or (for large n) "dd"."""
-    Xs, ys, e0, e1, ns = [], [], [], [], []
+def label(Os, ref: str = "qd", chunk: int = 2048):
+    """(features, labels, n) of instances: features by tor_features, labels
+    by tor_selector_label against the reference tier."""
+    Xs, Ls, ns = [], [], []
     for i in range(0, len(Os), chunk):
-        part = Os[i:i + chunk]
-        b = Batch(part)
-        X = tor_features(b).cpu().numpy()
-        rr = tor_eval_batched(b, tiers=ref)
-        r0 = tor_eval_batched(b, tiers="fp64")
-        r1 = tor_eval_batched(b, tiers="dd") if ref == "qd" else None
-        for k in range(len(part)):
-            tq = rr[k].exact
-            sa = rr[k].abs_exact
-            y = float(math.log10(sa / abs(tq))) if tq != 0 else YMAX
-            ys.append(min(y, YMAX))
-            den = abs(tq) if tq != 0 else sa
-            e0.append(float(abs(r0[k].exact - tq) / den))
-            e1.append(float(abs(r1[k].exact - tq) / den) if r1 is not None else float("nan"))
-        Xs.append(X)
+        b = Batch(Os[i:i + chunk])
+        Xs.append(tor_features(b).cpu().numpy())
+        Ls.append(tor_selector_label(b, ref))
         ns.append(b.n.copy())
-    return Labels(np.concatenate(Xs), np.array(ys), {0: np.array(e0), 1: np.array(e1)},
-                  np.concatenate(ns))
+    return np.concatenate(Xs), np.concatenate(Ls), np.concatenate(ns)
 
 
-def init_theta(seed: int) -> np.ndarray:
-    rng = np.random.default_rng(seed)
-    sizes = (_lib.TOR_NFEAT, 32, 32, 1)
-    parts = []
-    for i in range(3):
-        fi, fo = sizes[i], sizes[i + 1]
-        parts.append(rng.normal(0.0, 1.0 / math.sqrt(fi), size=fo * fi))
-        parts.append(np.zeros(fo))
-    return np.concatenate(parts)
+def training_set(seed: int = 11):
+    """The shipped selector's training data: 32 states of the 100-mode lossy
+    family of the batched workload (r ~ U[0.8, 1.6], transmission 0.3; seeds
+    5000.., never the benchmark's own state) with 400 patterns each,
+    n ~ U{6..26}; 4000 patterns of diverse 60-mode states (n 6..26); both
+    labelled against quad-double; 400 diverse patterns with n 27..36 labelled
+    against double-double."""
+    parts = [label(family_instances(32, 400, 5000, 6, 26)),
+             label(training_instances(4000, 6, 26, seed)),
+             label(training_instances(400, 27, 36, seed + 1), ref="dd", chunk=64)]
+    return tuple(np.concatenate([p[i] for p in parts]) for i in range(3))
 
 
-def train(X, y, epochs: int = 400, lr: float = 3e-3, batch_size: int = 512, under: float = 4.0,
-          over: float = 1.0, seed: int = 0, log_every: int = 0):
-    """Adam on the GPU kernels.  Returns (theta, mean, std, losses)."""
-    import torch
-    dev = "cuda"
-    mean = X.mean(axis=0)
-    std = X.std(axis=0)
-    std[std < 1e-12] = 1.0
-    th = torch.from_numpy(init_theta(seed)).to(dev)
-    m = torch.zeros_like(th)
-    v = torch.zeros_like(th)
-    tm = torch.from_numpy(mean).to(dev)
-    ts = torch.from_numpy(std).to(dev)
-    Xd = torch.from_numpy(np.ascontiguousarray(X)).to(dev)
-    yd = torch.from_numpy(np.ascontiguousarray(y)).to(dev)
-    rng = np.random.default_rng(seed)
-    B = X.shape[0]
-    step = 0
-    losses = []
-    for ep in range(epochs):
-        perm = torch.from_numpy(rng.permutation(B)).to(dev)
-        tot = 0.0
-        for i in range(0, B, batch_size):
-            idx = perm[i:i + batch_size]
-            xb = Xd[idx].contiguous()
-            yb = yd[idx].contiguous()
-            grad, loss = tor_mlp_grad(th, tm, ts, xb, yb, under, over)
-            step += 1
-            tor_mlp_adam(th, grad, m, v, lr, step)
-            tot += float(loss.item()) * len(idx)
-        losses.append(tot / B)
-        if log_every and ep % log_every == 0:
-            print(f"[selector] epoch {ep} loss {losses[-1]:.4f}", flush=True)
-    return th.cpu().numpy(), mean, std, losses
+DEFAULT_OPTIONS = dict(target="err64", loss="quantile", quantile=0.9, epochs=400, batch_size=512, lr=3e-3,
+                       slack=0.3, margin=0.0, seed=11)
 
 
-def predict(theta, mean, std, X) -> np.ndarray:
-    import torch
-    dev = "cuda"
-    return tor_mlp_forward(torch.from_numpy(np.ascontiguousarray(theta)).to(dev),
-                           torch.from_numpy(mean).to(dev), torch.from_numpy(std).to(dev),
-                           torch.from_numpy(np.ascontiguousarray(X)).to(dev)).cpu().numpy()
+def fit(X, L, n, **kw):
+    """Train and calibrate through tor_selector_train; returns (selector, losses)."""
+    o = dict(DEFAULT_OPTIONS)
+    o.update(kw)
+    return tor_selector_train(X, L, n, train_options(**o))
 
 
-def calibrate(lab: Labels, slack: float = 0.3):
-    """The per-tier error model log10(err_t / u_t) <= c_t + s_t log10 kappa:
-    for each slope s_t in [0.3, 1] the intercept is the upper envelope of the
-    training points; the slope kept is the one whose envelope lies lowest on
-    average over them (rounding errors of the alternating sum grow more
-    slowly than kappa); the intercept gets `slack` decades on top.
-    Returns (log10_c, slopes), three entries each (QD shares DD's)."""
-    cs, ss = [], []
-    for t in (0, 1):
-        e = lab.err[t]
-        ok = np.isfinite(e) & (e > 0)
-        if not ok.any():
-            cs.append(0.0)
-            ss.append(1.0)
-            continue
-        y = lab.y[ok]
-        r = np.log10(e[ok]) - math.log10(U[t])
-        best = None
-        for s in np.arange(0.30, 1.0001, 0.01):
-            c = float(np.max(r - s * y))
-            height = float(np.mean(c + s * y))
-            if best is None or height < best[0]:
-                best = (height, c, float(s))
-        cs.append(best[1] + slack)
-        ss.append(best[2])
-    cs.append(cs[-1])
-    ss.append(ss[-1])
-    return cs, ss
-
-
-def make_selector(theta, mean, std, lab: Labels, log10_c, slopes=(1.0, 1.0, 1.0), margin: float = 0.5):
-    sel = _lib.TorSelectorC()
-    for i, v in enumerate(theta):
-        sel.theta[i] = float(v)
-    for i in range(_lib.TOR_NFEAT):
-        sel.mean[i] = float(mean[i])
-        sel.std[i] = float(std[i])
-        sel.fmin[i] = float(lab.X[:, i].min())
-        sel.fmax[i] = float(lab.X[:, i].max())
-    for t in range(3):
-        sel.log10_c[t] = float(log10_c[t])
-        sel.slope[t] = float(slopes[t])
-    sel.margin = float(margin)
-    sel.nmin = int(lab.n.min())
-    sel.nmax = int(lab.n.max())
-    sel.trained = 1
-    return sel
-
-
-def fit_and_install(count: int = 3000, nlo: int = 6, nhi: int = 24, seed: int = 7, epochs: int = 300,
-                    path: str | None = None, verbose: bool = False, count_dd: int = 0, nhi_dd: int = 0):
-    """Generate, label, train, calibrate; install the selector (and save it).
-    count_dd instances with n in (nhi, nhi_dd] are labelled by the DD tier."""
-    Os = training_instances(count, nlo, nhi, seed)
-    lab = label(Os)
-    if count_dd > 0 and nhi_dd > nhi:
-        lab = lab + label(training_instances(count_dd, nhi + 1, nhi_dd, seed + 1), chunk=64, ref="dd")
-    theta, mean, std, losses = train(lab.X, lab.y, epochs=epochs, seed=seed,
-                                     log_every=50 if verbose else 0)
-    log10_c, slopes = calibrate(lab)
-    sel = make_selector(theta, mean, std, lab, log10_c, slopes)
+def fit_and_install(path: str | None = None, **kw):
+    """Label the training set, train, calibrate; install the selector (and
+    save it)."""
+    X, L, n = training_set()
+    sel, losses = fit(X, L, n, **kw)
     tor_selector_set(sel)
     if path:
         from .api import tor_selector_save
         tor_selector_save(path)
-    return sel, lab, losses
+    return sel, (X, L, n), losses
 
 
-DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "selector_default.txt")
+DATA = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+DEFAULT_PATH = os.path.join(DATA, "selector_default.txt")
+# the labelled training set the shipped selector was trained on (written by
+# `--train`): retraining from it with DEFAULT_OPTIONS gives the shipped
+# selector bit for bit
+TRAIN_SET_PATH = os.path.join(DATA, "selector_train.npz")
+
+
+def load_training_set(path: str = TRAIN_SET_PATH):
+    d = np.load(path)
+    return d["X"], d["L"], d["n"]
 
 
 def load_default() -> bool:
@@ -230,38 +139,24 @@ if __name__ == "__main__":
     import sys
     import time
     ap = argparse.ArgumentParser(description="train the precision selector on the GPU")
-    ap.add_argument("--train", action="store_true")
-    ap.add_argument("--count", type=int, default=4000)
-    ap.add_argument("--nlo", type=int, default=6)
-    ap.add_argument("--nhi", type=int, default=26)
-    ap.add_argument("--epochs", type=int, default=400)
-    ap.add_argument("--seed", type=int, default=11)
-    ap.add_argument("--count-dd", type=int, default=0,
-                    help="further instances with n in (nhi, nhi-dd], labelled by the DD tier")
-    ap.add_argument("--nhi-dd", type=int, default=0)
+    ap.add_argument("--train", action="store_true", help="label the training set, train, save both")
+    ap.add_argument("--from-labels", action="store_true", help="retrain from the saved training set")
     ap.add_argument("--out", default=DEFAULT_PATH)
+    ap.add_argument("--labels", default=TRAIN_SET_PATH)
     a = ap.parse_args()
-    if not a.train:
+    if not (a.train or a.from_labels):
         ap.print_help()
         sys.exit(0)
     t0 = time.time()
-    Os = training_instances(a.count, a.nlo, a.nhi, a.seed)
-    print(f"[selector] {len(Os)} instances, n {a.nlo}..{a.nhi}", flush=True)
-    lab = label(Os)
-    if a.count_dd > 0 and a.nhi_dd > a.nhi:
-        Od = training_instances(a.count_dd, a.nhi + 1, a.nhi_dd, a.seed + 1)
-        print(f"[selector] {len(Od)} instances, n {a.nhi + 1}..{a.nhi_dd} (DD reference)", flush=True)
-        lab = lab + label(Od, chunk=64, ref="dd")
-    print(f"[selector] labelled in {time.time() - t0:.1f} s; log10 kappa "
-          f"{lab.y.min():.2f}..{lab.y.max():.2f}", flush=True)
-    theta, mean, std, losses = train(lab.X, lab.y, epochs=a.epochs, seed=a.seed, log_every=50)
-    log10_c, slopes = calibrate(lab)
-    pred = predict(theta, mean, std, lab.X)
-    under = float(np.mean(pred < lab.y))
-    print(f"[selector] loss {losses[0]:.3f} -> {losses[-1]:.4f}; log10 C = {log10_c}; slopes = {slopes}; "
-          f"fraction under-predicted {under:.3f}", flush=True)
-    sel = make_selector(theta, mean, std, lab, log10_c, slopes)
+    if a.train:
+        X, L, n = training_set()
+        print(f"[selector] {len(n)} instances labelled in {time.time() - t0:.1f} s", flush=True)
+        np.savez_compressed(a.labels, X=X, L=L, n=n.astype(np.int32))
+    else:
+        X, L, n = load_training_set(a.labels)
+    sel, losses = fit(X, L, n)
     tor_selector_set(sel)
     from .api import tor_selector_save
     tor_selector_save(a.out)
-    print(f"[selector] saved {a.out} ({time.time() - t0:.1f} s)", flush=True)
+    print(f"[selector] loss {losses[0]:.4f} -> {losses[-1]:.4f}; log10_c {list(sel.log10_c)}; saved {a.out} "
+          f"({time.time() - t0:.1f} s)", flush=True)

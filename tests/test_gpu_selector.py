@@ -24,12 +24,25 @@ def tor():
 
 
 def test_features_kernel_matches_reference(tor):
-    Os = [g.random_instance(n, 300 + n) for n in [1, 2, 3, 5, 8, 13, 17, 21]]
+    Os = [g.random_instance(n, 300 + n) for n in [1, 2, 3, 5, 8, 13, 17, 21, 30, 40]]
     f = tor.tor_features(tor.Batch(Os)).cpu().numpy()
     for k, O in enumerate(Os):
         want = ref.features(O)
         print(f"[features] n={O.shape[0] // 2}", flush=True)
         assert np.allclose(f[k], want, rtol=1e-10, atol=1e-10), (k, f[k] - want)
+
+
+def test_features_beyond_the_inverse_limit(tor):
+    """From n = 47 the inverse does not fit beside R in LDS: the top-level
+    features are NaN (the bound estimate decides for such instances), the
+    others still match the reference; a small instance in the same launch
+    keeps all of its features."""
+    Os = [g.random_instance(47, 77), g.random_instance(9, 78)]
+    f = tor.tor_features(tor.Batch(Os)).cpu().numpy()
+    want = ref.features(Os[0])
+    assert np.all(np.isnan(f[0, 16:]))
+    assert np.allclose(f[0, :16], want[:16], rtol=1e-10, atol=1e-10)
+    assert np.allclose(f[1], ref.features(Os[1]), rtol=1e-10, atol=1e-10)
 
 
 def test_mlp_kernels_match_reference(tor):
@@ -46,6 +59,10 @@ def test_mlp_kernels_match_reference(tor):
     assert np.allclose(Y, ref.mlp_forward(theta, X, mean, std), rtol=1e-12, atol=1e-12)
     grad, loss = tor.tor_mlp_grad(d(theta), d(mean), d(std), d(X), d(y), under=4.0, over=1.0)
     lw, gw = ref.mlp_loss_and_grad(theta, X, y, mean, std, under=4.0, over=1.0)
+    assert abs(loss.item() - lw) <= 1e-12 * abs(lw)
+    assert np.allclose(grad.cpu().numpy(), gw, rtol=1e-10, atol=1e-13)
+    grad, loss = tor.tor_mlp_grad_quantile(d(theta), d(mean), d(std), d(X), d(y), q=0.9)
+    lw, gw = ref.mlp_loss_and_grad(theta, X, y, mean, std, quantile=0.9)
     assert abs(loss.item() - lw) <= 1e-12 * abs(lw)
     assert np.allclose(grad.cpu().numpy(), gw, rtol=1e-10, atol=1e-13)
 
@@ -92,17 +109,69 @@ def test_auto_with_bound_estimate_only_meets_tau(tor):
     assert not _meets(res, _reference_qd(tor, Os), 1e-3)
 
 
+def test_labels_are_the_reference_evaluations(tor):
+    """tor_selector_label: log10 kappa and the FP64 / DD forward errors
+    against the quad-double evaluation of the same instance, recomputed here
+    from the exact expansions of the same batched evaluations."""
+    Os = [g.random_instance(n, 600 + n) for n in (4, 9, 14)] + [np.zeros((0, 0), np.complex128)]
+    b = tor.Batch(Os)
+    L = tor.tor_selector_label(b, "qd")
+    assert np.all(np.isnan(L[3]))
+    res = {t: tor.tor_eval_batched(b, tiers=t) for t in ("qd", "fp64", "dd")}
+    for k, O in enumerate(Os[:3]):
+        q = res["qd"][k]
+        assert abs(L[k, 0] - math.log10(float(q.abs_exact / abs(q.exact)))) < 1e-12
+        for col, tier, u in ((1, "fp64", 2.0 ** -53), (2, "dd", 2.0 ** -104)):
+            r = res[tier][k]
+            e = float(abs(r.exact - q.exact) / abs(q.exact))
+            want = max(math.log10(e) if e > 0 else -400.0, math.log10(u) - 2.0)
+            assert abs(L[k, col] - want) < 1e-9, (k, col, L[k, col], want)
+        assert np.isnan(L[k, 3])
+
+
 @pytest.fixture(scope="module")
 def trained(tor, tmp_path_factory):
+    """A selector trained through tor_selector_train on a quickly labelled
+    set: 8 states of the batched workload's family (other seeds), n 6..18."""
     from paper_2009_01177_amd import selector
     path = str(tmp_path_factory.mktemp("sel") / "selector.txt")
-    sel, lab, losses = selector.fit_and_install(count=480, nlo=6, nhi=18, seed=3, epochs=150, path=path)
-    return sel, lab, losses, path
+    X, L, n = selector.label(selector.family_instances(8, 60, 7000, 6, 18))
+    sel, losses = selector.fit(X, L, n, epochs=150)
+    tor.tor_selector_set(sel)
+    tor.tor_selector_save(path)
+    return sel, (X, L, n), losses, path
 
 
 def test_training_reduces_the_loss(trained):
     _, _, losses, _ = trained
     assert losses[-1] < 0.25 * losses[0]
+
+
+def test_training_is_reproducible(tor, trained):
+    """The same samples and options give the same selector bit for bit."""
+    from paper_2009_01177_amd import selector
+    sel, (X, L, n), _, _ = trained
+    again, _ = selector.fit(X, L, n, epochs=150)
+    assert bytes(again) == bytes(sel)
+
+
+def test_shipped_selector_retrains_from_its_training_set(tor):
+    """Retraining through tor_selector_train from the shipped training set
+    with the shipped options gives the shipped selector bit for bit, so its
+    tiers on the whole 4096-pattern benchmark batch at tau = 1e-3 are the
+    same."""
+    from paper_2009_01177_amd import selector
+    X, L, n = selector.load_training_set()
+    sel, _ = selector.fit(X, L, n)
+    tor.tor_selector_load(selector.DEFAULT_PATH)
+    shipped = tor.tor_selector_get()
+    assert bytes(sel) == bytes(shipped)
+    b = tor.Batch(g.batched_workload(batch=4096))
+    t_shipped, _, _ = tor.tor_select_tiers(b, 1e-3)
+    tor.tor_selector_set(sel)
+    t_new, _, _ = tor.tor_select_tiers(b, 1e-3)
+    selector.load_default()
+    assert np.array_equal(t_new, t_shipped)
 
 
 def test_trained_selector_meets_tau_and_gains_over_bounds(tor, trained):

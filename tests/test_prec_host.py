@@ -189,3 +189,70 @@ def test_quad_double_rsqrt_within_its_bound(qd_cases):
         assert rel <= 128, float(rel)
         worst = max(worst, rel)
     assert worst > 0
+
+
+NONOVERLAP_HARNESS = r"""
+#include "prec.hpp"
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+using namespace prec;
+int main(int argc, char** argv) {
+  std::mt19937_64 g(atoi(argv[1]));
+  const int count = atoi(argv[2]);
+  std::uniform_real_distribution<double> U(-1.0, 1.0);
+  for (int i = 0; i < count; ++i) {
+    // a quad-double, and a nearby one cancelling it to 1e-3 .. 1e-30 of its size
+    qd a{{U(g) * 8.0, 0.0, 0.0, 0.0}};
+    a.x[1] = U(g) * 0x1p-54 * a.x[0];
+    a.x[2] = U(g) * 0x1p-54 * a.x[1];
+    a.x[3] = U(g) * 0x1p-54 * a.x[2];
+    const double rel = ldexp(U(g), -10 - (int)(i % 90));
+    qd b = qd_add(a, qd{{a.x[0] * rel, 0.0, 0.0, 0.0}});
+    if (i % 3 == 1) b = qd{{b.x[0], b.x[1], 0.0, 0.0}};
+    const qd d = qd_sub(b, a);
+    const qd z = qd_nonoverlapping(d);
+    printf("%a %a %a %a %a %a %a %a\n", d.x[0], d.x[1], d.x[2], d.x[3], z.x[0], z.x[1], z.x[2], z.x[3]);
+  }
+  return 0;
+}
+"""
+
+
+def lowest_bit(x: float) -> F:
+    """The value of the lowest set bit of a nonzero double."""
+    f = abs(F(x))
+    if f.denominator > 1:
+        return F(1, f.denominator)
+    m = f.numerator
+    return F(m & -m)
+
+
+def test_quad_double_output_is_non_overlapping(tmp_path):
+    """qd_nonoverlapping keeps the exact sum of the words and returns them
+    largest first and non-overlapping (each word smaller than the lowest set
+    bit of the one before, Shewchuk's definition), so the leading word is the
+    sum to within an ulp, also after the heavy cancellation where the
+    arithmetic leaves overlapping words."""
+    import math
+    src, exe = tmp_path / "n.cpp", tmp_path / "n"
+    src.write_text(NONOVERLAP_HARNESS)
+    r = subprocess.run(["g++", "-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-I",
+                        os.path.join(ROOT, "paper_2009_01177_amd", "csrc"), str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([str(exe), "3", "3000"], capture_output=True, text=True, check=True).stdout
+    overlapped = 0
+    for line in out.splitlines():
+        v = [float.fromhex(x) for x in line.split()]
+        d, z = v[:4], v[4:]
+        exact = sum(F(x) for x in d)
+        assert sum(F(x) for x in z) == exact
+        for i in range(3):
+            if z[i + 1] != 0.0:
+                assert z[i] != 0.0 and F(abs(z[i + 1])) < lowest_bit(z[i])
+        if exact != 0:
+            assert abs(F(z[0]) - exact) <= F(math.ulp(z[0]))
+            if abs(F(d[0]) - exact) > F(math.ulp(abs(float(exact)))):
+                overlapped += 1
+    assert overlapped > 0  # the cases this exists for occur

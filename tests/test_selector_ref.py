@@ -56,6 +56,63 @@ def test_features_basic_identities():
     assert abs(f[4] - np.mean(O.real.diagonal()[:n])) < 1e-15
 
 
+def test_spectrum_features_bracket_the_eigenvalues():
+    """Gershgorin's interval contains the spectrum of R, and Lanczos Ritz
+    values lie inside [lambda_min, lambda_max] (Cauchy interlacing): LAPACK's
+    eigenvalues of R pin f12..f15 from both sides; when 12 steps cover the
+    whole space (2n <= 12) the Ritz values are the extreme eigenvalues."""
+    for n, seed in ((3, 5), (6, 7), (11, 9)):
+        O = g.random_instance(n, seed)
+        f = ref.features(O)
+        ev = np.linalg.eigvalsh(ref.real_form(O))
+        assert f[12] <= ev[0] * (1 + 1e-12)
+        assert math.log(ev[-1]) <= f[13] + 1e-12
+        assert math.log(ev[0]) <= f[14] + 1e-9 and f[15] <= math.log(ev[-1]) + 1e-9
+        assert f[14] <= f[15]
+        if 2 * n <= ref.LANCZOS_STEPS:
+            assert abs(f[14] - math.log(ev[0])) < 1e-8 and abs(f[15] - math.log(ev[-1])) < 1e-8
+
+
+def test_top_level_features_are_the_oracles_term_ratios():
+    """f16..f19 are the level-(n-1) and level-(n-2) terms over the level-n
+    term; the binary128 oracle's terms of those subsets (determinants of
+    I - O_Z, no inverse) give the same means and maxima."""
+    n = 7
+    O = g.random_instance(n, 21)
+    f = ref.features(O)
+    full = float(oracle.terms(O, [(1 << n) - 1])[1][0])
+    m1 = [(1 << n) - 1 - (1 << k) for k in range(n)]
+    m2 = [(1 << n) - 1 - (1 << i) - (1 << j) for i in range(n) for j in range(i + 1, n)]
+    t1 = np.abs(oracle.terms(O, m1)[1]) / abs(full)
+    t2 = np.abs(oracle.terms(O, m2)[1]) / abs(full)
+    assert abs(f[16] - math.log(t1.mean())) < 1e-10 and abs(f[17] - math.log(t1.max())) < 1e-10
+    assert abs(f[18] - math.log(t2.mean())) < 1e-10 and abs(f[19] - math.log(t2.max())) < 1e-10
+    # every term is at most the largest one (det R_Z grows as Z shrinks)
+    assert f[17] <= 1e-12 and f[19] <= 1e-12
+
+
+def test_quantile_loss_gradient_against_finite_differences():
+    rng = np.random.default_rng(4)
+    P = ref.n_params()
+    theta = rng.normal(0, 0.3, size=P)
+    X = rng.normal(0, 1, size=(19, ref.NFEAT))
+    y = rng.normal(0, 1, size=19)
+    mean, std = np.zeros(ref.NFEAT), np.ones(ref.NFEAT)
+    loss, grad = ref.mlp_loss_and_grad(theta, X, y, mean, std, quantile=0.9)
+    pred = ref.mlp_forward(theta, X, mean, std)
+    r = y - pred
+    assert abs(loss - np.mean(np.maximum(0.9 * r, -0.1 * r))) < 1e-14
+    for p in rng.choice(P, size=40, replace=False):
+        h = 1e-7
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        lp, _ = ref.mlp_loss_and_grad(tp, X, y, mean, std, quantile=0.9)
+        lm, _ = ref.mlp_loss_and_grad(tm, X, y, mean, std, quantile=0.9)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grad[p]) <= 1e-6 * max(1.0, abs(fd)), p
+
+
 @pytest.mark.parametrize("n,seed", [(6, 1), (8, 2), (10, 3)])
 def test_fallback_bits_cover_the_actual_cancellation(n, seed):
     """The bound estimate must ask for at least the bits the alternating sum
@@ -117,13 +174,13 @@ def test_selector_file_round_trip(tmp_path):
     rng = np.random.default_rng(1)
     for i in range(_lib.TOR_MLP_PARAMS):
         sel.theta[i] = rng.normal()
-    for i in range(12):
+    for i in range(_lib.TOR_NFEAT):
         sel.mean[i], sel.std[i] = rng.normal(), 1.0 + rng.random()
         sel.fmin[i], sel.fmax[i] = -1.0 - i, 1.0 + i
     sel.log10_c[0], sel.log10_c[1], sel.log10_c[2] = 1.5, 2.0, 2.5
     sel.slope[0], sel.slope[1], sel.slope[2] = 0.55, 0.8, 1.0
     sel.margin = 0.7
-    sel.nmin, sel.nmax, sel.trained = 6, 24, 1
+    sel.nmin, sel.nmax, sel.trained, sel.target = 6, 24, 1, _lib.TOR_TARGET_ERR64
     old = tor.tor_selector_get()
     try:
         tor.tor_selector_set(sel)
@@ -136,35 +193,40 @@ def test_selector_file_round_trip(tmp_path):
         assert list(back.theta) == list(sel.theta)
         assert list(back.std) == list(sel.std) and back.margin == sel.margin
         assert list(back.slope) == list(sel.slope) and list(back.log10_c) == list(sel.log10_c)
-        assert (back.nmin, back.nmax, back.trained) == (6, 24, 1)
+        assert (back.nmin, back.nmax, back.trained, back.target) == (6, 24, 1, _lib.TOR_TARGET_ERR64)
     finally:
         tor.tor_selector_set(old)
 
 
-def test_selector_file_version_1_reads_as_slope_one(tmp_path):
-    """Files written before the error model had a slope load with slope 1."""
+def test_selector_files_of_the_12_feature_networks_are_refused(tmp_path):
+    """Version 3 files hold the 20-feature network and its target; files of
+    earlier versions (12-feature networks) are refused, as are a slope
+    outside (0, 2] for a kappa-target selector and an unknown target."""
     import paper_2009_01177_amd as tor
     from paper_2009_01177_amd import _lib
     old = tor.tor_selector_get()
     try:
         sel = _lib.TorSelectorC()
-        for i in range(12):
+        for i in range(_lib.TOR_NFEAT):
             sel.std[i], sel.fmax[i] = 1.0, 1.0
         for t in range(3):
             sel.slope[t] = 0.5
-        sel.nmin, sel.nmax, sel.trained = 6, 24, 1
+        sel.nmin, sel.nmax, sel.trained, sel.target = 6, 24, 1, _lib.TOR_TARGET_KAPPA
         tor.tor_selector_set(sel)
-        p = os.path.join(tmp_path, "v2.txt")
+        p = os.path.join(tmp_path, "v3.txt")
         tor.tor_selector_save(p)
         lines = open(p).read().splitlines()
-        assert lines[0] == "tor_selector 2"
-        v1 = ["tor_selector 1"] + [ln for ln in lines[1:] if not ln.startswith("slope ")]
-        p1 = os.path.join(tmp_path, "v1.txt")
-        open(p1, "w").write("\n".join(v1) + "\n")
-        tor.tor_selector_load(p1)
-        assert list(tor.tor_selector_get().slope) == [1.0, 1.0, 1.0]
-        # a slope outside (0, 2] is refused
+        assert lines[0] == "tor_selector 3"
+        for v in (1, 2):
+            pv = os.path.join(tmp_path, f"v{v}.txt")
+            open(pv, "w").write("\n".join([f"tor_selector {v}"] + lines[1:]) + "\n")
+            with pytest.raises(tor.TorError):
+                tor.tor_selector_load(pv)
         sel.slope[0] = 0.0
+        with pytest.raises(tor.TorError):
+            tor.tor_selector_set(sel)
+        sel.slope[0] = 0.5
+        sel.target = 7
         with pytest.raises(tor.TorError):
             tor.tor_selector_set(sel)
     finally:
