@@ -246,6 +246,15 @@ int tor_mcmc(const void* O_full, int32_t M, int64_t ld, int32_t N, int32_t chain
 int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
                          double* out_levels, tor_result_t* out);
 
+/* The same per-level sums through the Schur path's own kernels (the
+ * breadth-first top levels and the middle + bottom kernel in a level-sum
+ * mode: one wavefront per workgroup, bottoms of at most 4 / 3 / 2 modes in
+ * FP64 / DD / QD, every lane keeping one run per subset size and every
+ * wavefront adding its lanes' runs in lane order); arguments and output as
+ * tor_debug_level_sums, any n up to TOR_NMAX.  Synchronous. */
+int tor_debug_level_sums_schur(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
+                               double* out_levels, tor_result_t* out);
+
 /* det(I - O_Z)^(-1/2) with its sign (-1)^(n-|Z|) for k explicit subsets
  * (one term of Eq. 2 each).
  *   masks      device, k uint64 (bit i <=> mode i in Z, i < n)

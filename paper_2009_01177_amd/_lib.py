@@ -31,7 +31,7 @@ EXPORTS = (
     "tor_fallback_bits", "tor_select_tiers", "tor_last_select_stats",
     "tor_autotune", "tor_autotune_save", "tor_autotune_load", "tor_workspace_bytes",
     "tor_batch_workspace_bytes", "tor_eval_noalloc", "tor_noalloc_nmax",
-    "tor_mlp_grad_quantile", "tor_selector_label", "tor_selector_train",
+    "tor_mlp_grad_quantile", "tor_selector_label", "tor_selector_train", "tor_debug_level_sums_schur",
 )
 
 TOR_NFEAT = 20
@@ -169,6 +169,8 @@ def lib():
                            ctypes.POINTER(TorOptionsC), vp, vp, vp]
     L.tor_debug_level_sums.restype = ctypes.c_int
     L.tor_debug_level_sums.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
+    L.tor_debug_level_sums_schur.restype = ctypes.c_int
+    L.tor_debug_level_sums_schur.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
     L.tor_debug_sampled_terms.restype = ctypes.c_int
     L.tor_debug_sampled_terms.argtypes = [vp, i32, i64, i32, vp, i64, vp, vp]
     L.tor_last_kernel_ms.restype = ctypes.c_double

@@ -399,16 +399,17 @@ def tor_last_select_stats() -> dict:
     return {name: int(getattr(st, name)) for name, _ in st._fields_ if name != "reserved"}
 
 
-def tor_debug_level_sums(O, tier="dd", stream=None):
+def tor_debug_level_sums(O, tier="dd", stream=None, algo="border"):
     """(levels, result): levels[m] is L_m = sum over |Z| = m of det^(-1/2),
-    each as a Fraction of the returned expansion."""
+    each as a Fraction of the returned expansion; algo "border" (the
+    bordered kernel) or "schur" (the Schur path's kernels in their level-sum
+    mode)."""
     Od, n, ld = _device_o(O)
     lv = np.zeros(4 * (n + 1), dtype=np.float64)
     out = _lib.TorResultC()
-    rc = lib().tor_debug_level_sums(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier),
-                                    _stream_ptr(stream),
-                                    lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
-                                    ctypes.byref(out))
+    fn = {"border": lib().tor_debug_level_sums, "schur": lib().tor_debug_level_sums_schur}[algo]
+    rc = fn(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), _stream_ptr(stream),
+            lv.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(out))
     check(rc, "tor_debug_level_sums")
     levels = [sum((Fraction(x) for x in lv[4 * m:4 * m + 4]), Fraction(0)) for m in range(n + 1)]
     return levels, _res(out)

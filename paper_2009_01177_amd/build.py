@@ -40,18 +40,41 @@ def up_to_date() -> bool:
     return all(os.path.getmtime(p) <= t for p in deps())
 
 
-def build(force: bool = True, verbose: bool = False) -> str:
-    if not force and up_to_date():
-        return LIB
-    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc] + FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + sources()
+OBJ_DIR = os.path.join(HERE, "_build")
+
+
+def _run(cmd, verbose):
     if verbose:
         print(" ".join(cmd), flush=True)
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    """Compile every source to an object (in parallel, one hipcc per
+    source: each object carries its own gfx950 code), then link the shared
+    library."""
+    if not force and up_to_date():
+        return LIB
+    from concurrent.futures import ThreadPoolExecutor
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+    jobs = []
+    for src in sources():
+        obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
+        jobs.append((obj, [hipcc] + cflags + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]))
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
+    with ThreadPoolExecutor(workers) as ex:
+        results = list(ex.map(lambda j: _run(j[1], verbose), jobs))
+    for (obj, cmd), r in zip(jobs, results):
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed (%d) on %s" % (r.returncode, cmd[-3]))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    r = _run([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [o for o, _ in jobs], verbose)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed (%d)" % r.returncode)
+        raise RuntimeError("hipcc link failed (%d)" % r.returncode)
     os.replace(tmp, LIB)
     return LIB
 

@@ -449,12 +449,23 @@ int fold(int tier, const void* part, int nseg, size_t seg_len, void* out, void* 
 // instance k; results go to out[out_index ? out_index[k] : k] (device).
 // With one instance, only the depth-D_s states [z_lo, z_hi) are expanded and
 // summed (a share of the evaluation; the whole of it by default).
+// Level-sum debug mode: device buffers of the per-workgroup level sums of
+// one chunk (grid x (n+1)), the per-chunk sums (nchunks x (n+1)), the
+// result (n+1) and the reductions' scratch.
+struct LevelOut {
+  char* part;
+  char* chunks;
+  char* out;
+  char* scratch;
+};
+
 // B is the plan's base (p.bytes of device memory), cus the device's compute
 // units; w (may be NULL) receives the kernel timing events and launch shape.
+// lv (single instance, whole evaluation) also runs the level-sum mode.
 int enqueue_schur_group(Workspace* w, char* B, int cus, const SchurPlan& p, const void* O,
                         const int64_t* offs_dev, int64_t ld, const tor_options_t* opt,
                         const int32_t* out_index, tor_result_t* out, bool timed, hipStream_t s,
-                        size_t z_lo = 0, size_t z_hi = SIZE_MAX) {
+                        size_t z_lo = 0, size_t z_hi = SIZE_MAX, const LevelOut* lv = nullptr) {
   const int tier = p.tier, n = p.n;
   const bool whole = z_lo == 0 && z_hi >= p.Ns;
   if (!whole && (p.R != 1 || z_lo >= z_hi || z_hi > p.Ns)) return TOR_EINVAL;
@@ -462,8 +473,10 @@ int enqueue_schur_group(Workspace* w, char* B, int cus, const SchurPlan& p, cons
   if (timed && !w) return TOR_EINVAL;
   uint32_t* cnt = (uint32_t*)(B + p.o_cnt);
   int32_t* status = (int32_t*)(cnt + 1);
+  if (lv && (p.R != 1 || !whole)) return TOR_EINVAL;
   int occ = 0;
-  TOR_HIP(leaf_occupancy(tier, p.s_b, &occ));
+  if (lv) TOR_HIP(leaf_levels_occupancy(tier, p.s_b, &occ));
+  else TOR_HIP(leaf_occupancy(tier, p.s_b, &occ));
   if (occ < 1) return TOR_EUNSUPPORTED;
   int grid = (opt && opt->grid > 0) ? opt->grid : occ * cus;
   if ((size_t)grid > p.mids) grid = (int)p.mids;
@@ -525,14 +538,21 @@ int enqueue_schur_group(Workspace* w, char* B, int cus, const SchurPlan& p, cons
     const int32_t* ln = cur < 0 ? in_ : (const int32_t*)(B + p.o_n[cur]);
     const int nm = cr << p.Dl;
     if (timed) TOR_TRY(record_ev(w, 2 * w->ev_pairs, s));
-    TOR_HIP(launch_leaf(tier, p.s_m, p.s_b, lm, lg, ln, nm, n, B + p.o_part, status,
-                        std::min(grid, nm), s));
+    if (lv) {
+      const int blocks = std::min(grid, nm);
+      TOR_HIP(launch_leaf_levels(tier, p.s_m, p.s_b, lm, lg, ln, nm, n, B + p.o_part, status, blocks, lv->part, s));
+      TOR_HIP(launch_reduce_cols(tier, lv->part, blocks, n + 1, lv->chunks + ab * (n + 1) * (first / p.Cr),
+                                 lv->scratch, s));
+    } else {
+      TOR_HIP(launch_leaf(tier, p.s_m, p.s_b, lm, lg, ln, nm, n, B + p.o_part, status, std::min(grid, nm), s));
+    }
     if (timed) {
       TOR_TRY(record_ev(w, 2 * w->ev_pairs + 1, s));
       w->ev_pairs += 1;
     }
     TOR_TRY(fold(tier, B + p.o_part, cr, (size_t)1 << p.Dl, B + p.o_ds + ab * 2 * first, B + p.o_rsc, s));
   }
+  if (lv) TOR_HIP(launch_reduce_cols(tier, lv->chunks, p.nchunks, n + 1, lv->out, lv->scratch, s));
   if (whole)
     TOR_TRY(fold(tier, B + p.o_ds, p.R, (size_t)1 << p.D_s, B + p.o_inst, B + p.o_rsc, s));
   else
@@ -1638,6 +1658,51 @@ int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, voi
   const size_t ab = acc_bytes(tier);
   TOR_HIP(hipMemcpyAsync(w->host_res, ro.dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
   TOR_HIP(hipMemcpyAsync(w->host_lev, (char*)ro.red + 2 * ab, ab * (n + 1), hipMemcpyDeviceToHost, s));
+  TOR_HIP(hipStreamSynchronize(s));
+  *out = *w->host_res;
+  const int per = (int)(ab / sizeof(double));
+  for (int m = 0; m <= n; ++m) {
+    prec::qd v{{0.0, 0.0, 0.0, 0.0}};
+    for (int k = 0; k < per && k < 4; ++k) v.x[k] = w->host_lev[per * m + k];
+    if (per == 4) v = prec::qd_nonoverlapping(v);
+    for (int k = 0; k < 4; ++k) out_levels[4 * m + k] = v.x[k];
+  }
+  return out->status;
+}
+
+int tor_debug_level_sums_schur(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
+                               double* out_levels, tor_result_t* out) {
+  if (out == nullptr || out_levels == nullptr) return TOR_EINVAL;
+  TOR_TRY(check_common(O, n, ld, tier));
+  if (n == 0) {
+    fill_trivial(out, tier);
+    out_levels[0] = 1.0;
+    out_levels[1] = out_levels[2] = out_levels[3] = 0.0;
+    return TOR_OK;
+  }
+  Workspace* w = nullptr;
+  TOR_TRY(get_ws(&w));
+  hipStream_t s = (hipStream_t)stream;
+  SchurPlan p;
+  plan_schur(tier, n, 1, level_sb_max(tier), &p);
+  int occ = 0;
+  TOR_HIP(leaf_levels_occupancy(tier, p.s_b, &occ));
+  if (occ < 1) return TOR_EUNSUPPORTED;
+  const size_t ab = acc_bytes(tier), cols = (size_t)n + 1;
+  const size_t grid = std::min((size_t)occ * w->cus, p.mids);
+  Carver c;
+  c.off = p.bytes;
+  const size_t o_part = c.take(ab * cols * grid), o_chunks = c.take(ab * cols * p.nchunks);
+  const size_t o_out = c.take(ab * cols);
+  const size_t o_sc = c.take(reduce_scratch_bytes(tier, (int)std::max(grid, (size_t)p.nchunks), (int)cols));
+  TOR_TRY(ensure_cap(w, c.off));
+  LevelOut lv{w->buf + o_part, w->buf + o_chunks, w->buf + o_out, w->buf + o_sc};
+  tor_result_t* dres = (tor_result_t*)(w->buf + p.o_res);
+  w->ev_pairs = 0;
+  TOR_TRY(enqueue_schur_group(w, w->buf, w->cus, p, O, nullptr, ld, nullptr, nullptr, dres, false, s, 0, SIZE_MAX,
+                              &lv));
+  TOR_HIP(hipMemcpyAsync(w->host_res, dres, sizeof(tor_result_t), hipMemcpyDeviceToHost, s));
+  TOR_HIP(hipMemcpyAsync(w->host_lev, lv.out, ab * cols, hipMemcpyDeviceToHost, s));
   TOR_HIP(hipStreamSynchronize(s));
   *out = *w->host_res;
   const int per = (int)(ab / sizeof(double));

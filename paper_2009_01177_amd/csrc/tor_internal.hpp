@@ -93,6 +93,15 @@ size_t expand_multi_lds_bytes(int tier, int s, int K);
 hipError_t launch_expand_multi(int tier, const void* in_mat, const void* in_g, const int32_t* in_m,
                                int s, int K, int nst, void* out_mat, void* out_g, int32_t* out_m,
                                int32_t* status, hipStream_t st);
+// Level-sum debug mode of the middle + bottom kernel: as launch_leaf, and
+// every workgroup (one wavefront) writes its level sums of |terms| by subset
+// size, lvpart[block][0..n] (accumulators), for the states it took.  Bottom
+// sizes 1..level_sb_max(tier).
+int level_sb_max(int tier);
+hipError_t launch_leaf_levels(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
+                              int nst, int n, void* partials, int32_t* status, int grid, void* lvpart,
+                              hipStream_t st);
+hipError_t leaf_levels_occupancy(int tier, int s_b, int* blocks_per_cu);
 hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
                        int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st);
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu);

@@ -81,17 +81,20 @@ __device__ __forceinline__ qd r_from_sum<qd>(double a, double b, double c) {
 // relative to the lane's state (p[0]: even, p[1]: odd).  Every term g =
 // det^(-1/2) is positive, so one run per parity gives both the signed sum
 // (the difference of the two, its sign set by (-1)^(n-|Z|)) and the sum of
-// magnitudes (their sum) with one accumulation per term.
-template <class TT>
+// magnitudes (their sum) with one accumulation per term.  NL > 0 (the
+// level-sum debug mode) adds one run per relative subset size 0..NL-1.
+template <class TT, int NL = 0>
 struct LaneAcc {
   typename TT::Acc p[2];
+  typename TT::Acc lv[NL > 0 ? NL : 1];
 };
 
-// Emit the term g of a completed subset whose size has parity PAR relative
-// to the lane's state.
-template <class TT, int PAR>
-__device__ __forceinline__ void emit_term(LaneAcc<TT>& acc, const typename TT::R& g) {
-  acc.p[PAR] = TT::acc_run(acc.p[PAR], g);
+// Emit the term g of a completed subset whose size exceeds the lane state's
+// by D.
+template <class TT, int D, int NL>
+__device__ __forceinline__ void emit_term(LaneAcc<TT, NL>& acc, const typename TT::R& g) {
+  acc.p[D & 1] = TT::acc_run(acc.p[D & 1], g);
+  if constexpr (NL > 0) acc.lv[D] = TT::acc_run(acc.lv[D], g);
 }
 
 // Pivot of the 2x2 block at rows (2i, 2i+1): reciprocal square roots of the
@@ -154,8 +157,8 @@ struct Bottom {
   using R = typename TT::R;
 
   // PAR: parity of the state's subset size relative to the lane's state
-  template <int I, int PAR>
-  __device__ __forceinline__ static void child(const R (&T)[psize(S)], const R& g, LaneAcc<TT>& acc,
+  template <int I, int D, int NL>
+  __device__ __forceinline__ static void child(const R (&T)[psize(S)], const R& g, LaneAcc<TT, NL>& acc,
                                                bool& bad) {
     constexpr int SC = S - 1 - I;
     constexpr int O = 2 * I + 2;
@@ -164,7 +167,7 @@ struct Bottom {
       const R& p00 = T[pk(2 * I, 2 * I)];
       const R det = r_det2(p00, T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
       if (!(r_lead(p00) > 0.0 && r_lead(det) > 0.0)) bad = true;
-      emit_term<TT, PAR ^ 1>(acc, r_mul(g, r_rsqrt(det)));
+      emit_term<TT, D + 1>(acc, r_mul(g, r_rsqrt(det)));
     } else {
       const Pivot<R> pv = make_pivot(T[pk(2 * I, 2 * I)], T[pk(2 * I + 1, 2 * I)], T[pk(2 * I + 1, 2 * I + 1)]);
       if (!pv.ok) bad = true;
@@ -183,21 +186,22 @@ struct Bottom {
           C[pk(a, b)] = r_fms2(T[pk(a + O, b + O)], u0[a], u0[b], u1[a], u1[b]);
         }
       }
-      Bottom<TT, SC>::template run<PAR ^ 1>(C, gc, acc, bad);
+      Bottom<TT, SC>::template run<D + 1>(C, gc, acc, bad);
     }
   }
 
-  template <int I, int PAR>
-  __device__ __forceinline__ static void children(const R (&T)[psize(S)], const R& g, LaneAcc<TT>& acc,
+  template <int I, int D, int NL>
+  __device__ __forceinline__ static void children(const R (&T)[psize(S)], const R& g, LaneAcc<TT, NL>& acc,
                                                   bool& bad) {
-    child<I, PAR>(T, g, acc, bad);
-    if constexpr (I > 0) children<I - 1, PAR>(T, g, acc, bad);
+    child<I, D>(T, g, acc, bad);
+    if constexpr (I > 0) children<I - 1, D>(T, g, acc, bad);
   }
 
-  template <int PAR>
-  __device__ __forceinline__ static void run(const R (&T)[psize(S)], const R& g, LaneAcc<TT>& acc, bool& bad) {
-    emit_term<TT, PAR>(acc, g);
-    children<S - 1, PAR>(T, g, acc, bad);
+  // D: the state's subset size over the lane state's
+  template <int D, int NL>
+  __device__ __forceinline__ static void run(const R (&T)[psize(S)], const R& g, LaneAcc<TT, NL>& acc, bool& bad) {
+    emit_term<TT, D>(acc, g);
+    children<S - 1, D>(T, g, acc, bad);
   }
 };
 
@@ -800,13 +804,31 @@ struct Leaf {
   }
 
   // The bottom of the lane's state and the wave's fixed-order totals,
-  // stored as state z's partial.
+  // stored as state z's partial.  LV (the level-sum debug mode): every
+  // lane also keeps one run per relative subset size, and the wave adds
+  // them into its level sums lvs[0..n] (LDS) lane by lane in lane order.
+  template <bool LV = false>
   __device__ __forceinline__ static void finish(const R (&leaf)[psize(SB)], const R& lg, int32_t lm, int L,
-                                                int lane, int n, int z, Acc* partials, bool& bad) {
-    LaneAcc<TT> acc;
+                                                int lane, int n, int z, Acc* partials, bool& bad,
+                                                Acc* lvs = nullptr) {
+    LaneAcc<TT, LV ? SB + 1 : 0> acc;
     acc.p[0] = TT::acc_zero();
     acc.p[1] = TT::acc_zero();
+    if constexpr (LV) {
+#pragma unroll
+      for (int d = 0; d <= SB; ++d) acc.lv[d] = TT::acc_zero();
+    }
     if (lane < (1 << L)) Bottom<TT, SB>::template run<0>(leaf, lg, acc, bad);
+    if constexpr (LV) {
+      for (int l = 0; l < (1 << L); ++l) {
+        const int ml = __builtin_amdgcn_readlane(lm, l);
+#pragma unroll
+        for (int d = 0; d <= SB; ++d) {
+          const Acc x = lane_bcast(TT::acc_fix(acc.lv[d]), l);
+          if (lane == 0) lvs[ml + d] = TT::acc_merge(lvs[ml + d], x);
+        }
+      }
+    }
     // the lane's state has |Z| = lm: its own term has sign (-1)^(n - lm)
     const Acc pe = TT::acc_fix(acc.p[0]), po = TT::acc_fix(acc.p[1]);
     const bool odd = ((n - lm) & 1) != 0;
@@ -849,22 +871,29 @@ constexpr bool leaf_pair_in_registers() {
   return W == 2 && ((TT::id == TOR_DD && SB == 4) || (TT::id == TOR_FP64 && SB == 6));
 }
 
-template <class TT, int SB, int W>
+template <class TT, int SB, int W, bool LV = false>
 __global__ __launch_bounds__(64 * W)
 __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf_kernel(const typename TT::R* __restrict__ mat,
                                                       const typename TT::R* __restrict__ gin,
                                                       const int32_t* __restrict__ min_, int s_m,
                                                       int nstates, int n,
                                                       typename TT::Acc* __restrict__ partials,
-                                                      int32_t* __restrict__ status) {
+                                                      int32_t* __restrict__ status,
+                                                      typename TT::Acc* __restrict__ lvpart = nullptr) {
   using R = typename TT::R;
   using LF = Leaf<TT, SB>;
   using SMEM = typename LF::SMEM;
   static_assert(SMEM::max_items() * psize(SMEM::SM) < (1 << 20), "DivBy range");
   static_assert(W == 1 || W == 2, "one or two wavefronts");
+  static_assert(!LV || W == 1, "the level-sum mode runs one wavefront per workgroup");
   __shared__ SMEM sm;
+  // level sums of the wavefront (level-sum mode only)
+  __shared__ typename TT::Acc lvs[LV ? TOR_NMAX + 1 : 1];
   const int wv = (int)threadIdx.x >> 6;
   const int lane = (int)threadIdx.x & 63;
+  if constexpr (LV) {
+    for (int m = lane; m <= n; m += 64) lvs[m] = TT::acc_zero();
+  }
   for (int q = (int)threadIdx.x; q < (SMEM::SM - 1) * SMEM::SM / 2; q += 64 * W) {
     int i = 0;
     while ((i + 1) * (i + 2) / 2 <= q) ++i;
@@ -903,11 +932,15 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
     if (W == 2) __syncthreads(); else wave_sync();
     if (z < nstates) {
       if constexpr (PR) LF::last_level(P, pg, pm, L, lane, bad, leaf, lg, lm);
-      LF::finish(leaf, lg, lm, L, lane, n, z, partials, bad);
+      LF::template finish<LV>(leaf, lg, lm, L, lane, n, z, partials, bad, lvs);
     }
     if (W == 2) __syncthreads();
   }
   if (W == 2 && wv == 0) __syncthreads();
+  if constexpr (LV) {
+    wave_sync();
+    for (int m = lane; m <= n; m += 64) lvpart[(size_t)blockIdx.x * (n + 1) + m] = lvs[m];
+  }
   if (bad) atomicOr(status, 1);
 }
 
@@ -1093,6 +1126,47 @@ hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* 
 #define CALL(TT, SBV) launch_leaf_t<TT, SBV>(mat, g, m, s_m, nst, n, partials, status, grid, st)
   TOR_LEAF_DISPATCH(CALL)
 #undef CALL
+}
+
+// Level-sum debug mode: one wavefront per workgroup, bottoms of at most
+// LEVEL_SB_MAX(tier) modes (their level runs need registers).
+template <class TT, int SB>
+static hipError_t launch_leaf_levels_t(const void* mat, const void* g, const int32_t* m, int s_m, int nst, int n,
+                                       void* partials, int32_t* status, int grid, void* lvpart, hipStream_t st) {
+  using R = typename TT::R;
+  using Acc = typename TT::Acc;
+  const int blocks = grid < nst ? grid : nst;
+  hipLaunchKernelGGL((leaf_kernel<TT, SB, 1, true>), dim3(blocks), dim3(64), 0, st, (const R*)mat, (const R*)g, m,
+                     s_m, nst, n, (Acc*)partials, status, (Acc*)lvpart);
+  return hipGetLastError();
+}
+
+int level_sb_max(int tier) { return tier == TOR_FP64 ? 4 : (tier == TOR_DD ? 3 : 2); }
+
+hipError_t launch_leaf_levels(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
+                              int nst, int n, void* partials, int32_t* status, int grid, void* lvpart,
+                              hipStream_t st) {
+  if (s_m < s_b || s_m - s_b > 6) return hipErrorInvalidValue;
+#define LV_CASE(TID, TT, SBV)                                                                                 \
+  if (tier == TID && s_b == SBV)                                                                             \
+    return launch_leaf_levels_t<TT, SBV>(mat, g, m, s_m, nst, n, partials, status, grid, lvpart, st);
+  LV_CASE(TOR_FP64, TierF64, 1) LV_CASE(TOR_FP64, TierF64, 2) LV_CASE(TOR_FP64, TierF64, 3)
+  LV_CASE(TOR_FP64, TierF64, 4) LV_CASE(TOR_DD, TierDD, 1) LV_CASE(TOR_DD, TierDD, 2) LV_CASE(TOR_DD, TierDD, 3)
+  LV_CASE(TOR_QD, TierQD, 1) LV_CASE(TOR_QD, TierQD, 2)
+#undef LV_CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t leaf_levels_occupancy(int tier, int s_b, int* blocks_per_cu) {
+#define LV_OCC(TID, TT, SBV)                                                                                   \
+  if (tier == TID && s_b == SBV)                                                                              \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                                      \
+        blocks_per_cu, reinterpret_cast<const void*>(&leaf_kernel<TT, SBV, 1, true>), 64, 0);
+  LV_OCC(TOR_FP64, TierF64, 1) LV_OCC(TOR_FP64, TierF64, 2) LV_OCC(TOR_FP64, TierF64, 3)
+  LV_OCC(TOR_FP64, TierF64, 4) LV_OCC(TOR_DD, TierDD, 1) LV_OCC(TOR_DD, TierDD, 2) LV_OCC(TOR_DD, TierDD, 3)
+  LV_OCC(TOR_QD, TierQD, 1) LV_OCC(TOR_QD, TierQD, 2)
+#undef LV_OCC
+  return hipErrorInvalidValue;
 }
 
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu) {

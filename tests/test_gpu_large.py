@@ -88,6 +88,22 @@ def test_block_diagonal_closed_form_full_size(tor, n):
     assert float(abs(res.exact - prod) / sabs) <= 1e-25
 
 
+@pytest.mark.parametrize("tier,tol", [("dd", 1e-27), ("fp64", 1e-12)])
+def test_extreme_level_sums_at_n30_through_the_schur_kernels(tor, tier, tol):
+    """P14 at the full size on the generic coupled benchmark instance: the
+    per-level sums L_m, m <= 4 and m >= 26 (63,862 subsets), from the Schur
+    path's kernels in their level-sum mode against the binary128 oracle's
+    level sums of the same subsets."""
+    O, _ = g.workload("n30_lossy")
+    ms = [0, 1, 2, 3, 4, 26, 27, 28, 29, 30]
+    print(f"[large] n=30 level sums {ms} via schur, tier={tier}", flush=True)
+    levels, res = tor.tor_debug_level_sums(O, tier=tier, algo="schur")
+    want = oracle.level_sums(O, ms)
+    for m, w in zip(ms, want):
+        assert float(abs(levels[m] - w) / w) <= tol, m
+    assert res.status == 0
+
+
 def test_tiers_agree_on_the_n30_workload(tor):
     """FP64 and DD against QD on the benchmark's own instance (kappa 2.6e21)."""
     O, _ = g.workload("n30_lossy")

@@ -240,6 +240,20 @@ def test_level_sums(tor, tier):
 
 
 @pytest.mark.parametrize("tier", ["fp64", "dd", "qd"])
+@pytest.mark.parametrize("n,seed", [(1, 3), (5, 8), (12, 31), (15, 32)])
+def test_level_sums_through_the_schur_kernels(tor, tier, n, seed):
+    """Per-level sums L_m from the Schur path's own kernels (level-sum mode)
+    against the binary128 oracle's, every level; the signed total against
+    the oracle's Torontonian."""
+    O = g.random_instance(n, seed)
+    ref = oracle.tor(O, level_sums=True)
+    levels, res = tor.tor_debug_level_sums(O, tier=tier, algo="schur")
+    for m in range(n + 1):
+        assert float(abs(levels[m] - ref["levels"][m]) / ref["levels"][m]) < max(TOL[tier], 1e-30), m
+    assert err_rel(res, ref) <= TOL[tier]
+
+
+@pytest.mark.parametrize("tier", ["fp64", "dd", "qd"])
 def test_sampled_terms_at_n30(tor, tier):
     """Per-subset terms at the full n = 30 against the oracle's binary128
     determinants (the bordered update on a generic coupled state)."""

@@ -116,30 +116,48 @@ def test_interrupted_run_resumes_from_its_checkpoint(tor, tmp_path):
     assert float(abs(total.exact - whole.exact) / whole.abs_exact) <= 1e-25
 
 
-def test_a_share_of_the_benchmark_instance_against_the_oracle(tor):
-    # the n = 30 benchmark instance through the timed kernels (the default
-    # bottom sizes and launch shape): the share of 1024 whose decisions on
-    # modes 0..9 are "in, out x8, in" (2^20 subsets), against the binary128
-    # oracle's terms for exactly those subsets
+def _share_against_the_oracle(tor, O, code, k, tiers=("dd", "fp64")):
+    """The share `code` of 2^k of instance O through the timed kernels (the
+    default bottom sizes and launch shape) against the binary128 oracle's
+    terms for exactly the subsets whose decisions on modes 0..k-1 spell
+    `code` (mode 0 the most significant bit)."""
     import math
-    O, _ = g.workload("n30_lossy")
-    nparts, k = 1024, 10
-    code = 0b1000000001
+    n = O.shape[0] // 2
     pre = 0
     for i in range(k):
         if (code >> (k - 1 - i)) & 1:
             pre |= 1 << i
-    masks = np.uint64(pre) | (np.arange(1 << 20, dtype=np.uint64) << np.uint64(k))
-    print("[parts] n=30 share 513 of 1024: oracle terms for 2^20 subsets", flush=True)
+    masks = np.uint64(pre) | (np.arange(1 << (n - k), dtype=np.uint64) << np.uint64(k))
+    print(f"[parts] n={n} share {code} of {1 << k}: oracle terms for 2^{n - k} subsets", flush=True)
     d3, t3, st = oracle._terms3(O, masks)
     assert (st == 0).all()
     want = sum(map(Fraction, t3.ravel()))
     sabs = math.fsum(np.abs(t3[:, 0]))
-    for tier in ("dd", "fp64"):
-        r = tor.tor_eval_part(O, code, nparts, tier=tier)
+    for tier in tiers:
+        r = tor.tor_eval_part(O, code, 1 << k, tier=tier)
         assert r.status == 0
         assert float(abs(r.exact - want)) <= TOL[tier] * sabs, tier
         assert abs(float(r.abs_exact) - sabs) <= 1e-12 * sabs
+
+
+@pytest.mark.parametrize("code", [0b1000000001, "seed-1", "seed-2"])
+def test_a_share_of_the_benchmark_instance_against_the_oracle(tor, code):
+    # the n = 30 benchmark instance: the share "in, out x8, in" of 1024 and
+    # two seeded shares with three modes in (2^20 subsets each)
+    O, _ = g.workload("n30_lossy")
+    if isinstance(code, str):
+        rng = np.random.default_rng(int(code[-1]))
+        bits = rng.choice(10, size=3, replace=False)
+        code = int(sum(1 << int(b) for b in bits))
+    _share_against_the_oracle(tor, O, code, 10)
+
+
+def test_the_all_in_share_of_the_benchmark_state(tor):
+    # the largest terms: every subset containing modes 0..9 (the all-in share
+    # of 1024), on 26 clicked modes of the benchmark's state (2^16 subsets;
+    # at n = 30 the oracle needs minutes for this share)
+    O, _ = g.workload("n30_lossy", n=26)
+    _share_against_the_oracle(tor, O, (1 << 10) - 1, 10)
 
 
 @pytest.mark.parametrize("tier", ["fp64", "dd", "qd"])
