@@ -275,12 +275,20 @@ double tor_last_kernel_ms(int32_t* split_depth, int32_t* grid, int32_t* launches
 /* ---- Autotuner -------------------------------------------------------------
  * The Schur path's only shape choice with a real trade-off is s_b, the modes
  * each lane finishes in registers (more registers per lane vs. fewer middle
- * levels in LDS).  The tuner times every compiled s_b for (n, tier) on a
- * synthetic instance (the work does not depend on the values) and makes the
- * fastest the default for that (n, tier) in this process. */
+ * levels in LDS).  The tuner times every compiled s_b for (n, tier) in the
+ * shape such evaluations run in: for n <= 24 a batch group of 256 instances
+ * (the batched workloads), for larger n one instance timed on a share of
+ * about 2^28 subsets of its kept frontier and scaled to the whole (so
+ * tuning at n = 50 takes seconds, not hours); the work does not depend on
+ * the values, so the instances are synthetic.  The fastest becomes the
+ * default for that (n, tier) in this process.  A table shipped beside the
+ * library (data/autotune_default.txt in its directory, written by tuning
+ * n = 1..40 on an MI355X) is read before the first evaluation; the
+ * environment variable TOR_AUTOTUNE_TABLE names another file (empty: none). */
 
 /* best_bottom: host, the chosen s_b; ms: host, 6 doubles (s_b = 1..6, -1
- * where not compiled for the tier), may be NULL.  Synchronous; 1 <= n <= TOR_NMAX. */
+ * where not compiled for the tier), the measured or scaled milliseconds, may
+ * be NULL.  Synchronous; 1 <= n <= TOR_NMAX. */
 int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, double* ms);
 /* Save / load the tuned table as text lines "n tier s_b". */
 int tor_autotune_save(const char* path);

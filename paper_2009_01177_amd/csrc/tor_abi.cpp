@@ -10,6 +10,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <map>
 #include <string>
@@ -75,8 +77,36 @@ std::map<int, Workspace*> g_ws;
 
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, int> g_tuned;  // (n, tier) -> s_b
+// tor_autotune times n <= AUTOTUNE_GROUP_NMAX as batch groups of this many
+// instances (the batched workloads' shape), larger n as single instances
+constexpr int AUTOTUNE_GROUP = 256;
+constexpr int AUTOTUNE_GROUP_NMAX = 24;
+
+int load_tune_table(const char* path);
+
+// The tuned table shipped beside the library (data/autotune_default.txt in
+// the library's directory), or the file TOR_AUTOTUNE_TABLE names (empty:
+// none), read once per process before the first plan.
+void load_default_tune_table() {
+  static std::once_flag once;
+  std::call_once(once, []() {
+    std::string path;
+    if (const char* e = getenv("TOR_AUTOTUNE_TABLE")) {
+      path = e;
+    } else {
+      Dl_info info;
+      if (dladdr(reinterpret_cast<const void*>(&load_default_tune_table), &info) && info.dli_fname) {
+        path = info.dli_fname;
+        const size_t slash = path.find_last_of('/');
+        path = (slash == std::string::npos ? std::string(".") : path.substr(0, slash)) + "/data/autotune_default.txt";
+      }
+    }
+    if (!path.empty()) (void)load_tune_table(path.c_str());
+  });
+}
 
 int tuned_bottom(int n, int tier) {
+  load_default_tune_table();
   std::lock_guard<std::mutex> lk(g_tune_mu);
   auto it = g_tuned.find(std::make_pair(n, tier));
   return it == g_tuned.end() ? 0 : it->second;
@@ -1394,15 +1424,33 @@ int tor_select_tiers(const void* O_packed, const int64_t* offsets, const int32_t
 
 int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, double* ms) {
   if (n < 1 || n > TOR_NMAX || (tier != TOR_FP64 && tier != TOR_DD && tier != TOR_QD)) return TOR_EINVAL;
+  load_default_tune_table();  // the result below overrides the shipped entry
   Workspace* w = nullptr;
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
-  // synthetic instance: O = 0.25 I (a thermal product), positive definite
-  std::vector<double> h((size_t)8 * n * n, 0.0);
-  for (int i = 0; i < 2 * n; ++i) h[2 * ((size_t)i * 2 * n + i)] = 0.25;
+  // the shape the evaluations of this n run as: up to n = 24 a batch group
+  // of R copies of one instance (the work does not depend on the values;
+  // a thermal product O = 0.25 I), larger n one instance, timed on a share
+  // of its depth-D_s frontier of about 2^28 subsets and scaled to the whole
+  const int R = n <= AUTOTUNE_GROUP_NMAX ? AUTOTUNE_GROUP : 1;
+  const size_t per = (size_t)4 * n * n;  // complex elements of one O
+  std::vector<double> h(2 * per * R, 0.0);
+  for (int r = 0; r < R; ++r)
+    for (int i = 0; i < 2 * n; ++i) h[2 * (per * r + (size_t)i * 2 * n + i)] = 0.25;
   double* dO = nullptr;
   TOR_HIP(hipMalloc((void**)&dO, sizeof(double) * h.size()));
   int rc = hip_err(hipMemcpy(dO, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice));
+  std::vector<int64_t> offs(R);
+  std::vector<int32_t> ns(R, n), ts(R, tier), idx(R);
+  for (int r = 0; r < R; ++r) {
+    offs[r] = (int64_t)(per * r);
+    idx[r] = r;
+  }
+  tor_result_t* dres = nullptr;
+  if (rc == TOR_OK) rc = hip_err(hipMalloc((void**)&dres, sizeof(tor_result_t) * R));
+  hipEvent_t ea = nullptr, eb = nullptr;
+  if (rc == TOR_OK) rc = hip_err(hipEventCreate(&ea));
+  if (rc == TOR_OK) rc = hip_err(hipEventCreate(&eb));
   const int cand_max = tier == TOR_FP64 ? 6 : (tier == TOR_DD ? 5 : 3);
   int best = 0;
   double best_ms = 1e300;
@@ -1414,32 +1462,43 @@ int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, do
     o.algo = TOR_ALGO_SCHUR;
     o.split_depth = -1;
     o.bottom_modes = sb;
-    o.flags = TOR_FLAG_TIME_KERNEL;
-    tor_result_t r;
+    // one run: the whole batch group, or the share [0, cnt) of the frontier
+    double scale = 1.0;
+    auto run = [&]() -> int {
+      if (R > 1) return batch_core(w, dO, offs.data(), ns.data(), idx, ts, &o, dres, false, s);
+      SchurPlan p;
+      plan_schur(tier, n, 1, sb, &p);
+      TOR_TRY(ensure_cap(w, p.bytes));
+      const int sub = n - p.D_s;  // subsets per frontier state: 2^sub
+      size_t cnt = sub >= 28 ? 1 : ((size_t)1 << (28 - sub));
+      cnt = std::max(cnt, (size_t)p.Cr);
+      cnt = std::min(cnt, p.Ns);
+      scale = (double)p.Ns / (double)cnt;
+      return enqueue_schur_group(w, w->buf, w->cus, p, dO, nullptr, 2 * (int64_t)n, &o, nullptr, dres, false, s, 0,
+                                 cnt);
+    };
     double tot = 0.0;
     for (int rep = 0; rep < 3 && rc == TOR_OK; ++rep) {
-      hipEvent_t a, b;
-      rc = hip_err(hipEventCreate(&a));
-      if (rc != TOR_OK) break;
-      rc = hip_err(hipEventCreate(&b));
-      if (rc == TOR_OK) rc = hip_err(hipEventRecord(a, s));
-      if (rc == TOR_OK) rc = tor_eval(dO, n, 2 * n, tier, &o, stream, &r);
-      if (rc == TOR_OK) rc = hip_err(hipEventRecord(b, s));
-      if (rc == TOR_OK) rc = hip_err(hipEventSynchronize(b));
+      rc = hip_err(hipEventRecord(ea, s));
+      if (rc == TOR_OK) rc = run();
+      if (rc == TOR_OK) rc = hip_err(hipEventRecord(eb, s));
+      if (rc == TOR_OK) rc = hip_err(hipEventSynchronize(eb));
       float t = 0.0f;
-      if (rc == TOR_OK) rc = hip_err(hipEventElapsedTime(&t, a, b));
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
+      if (rc == TOR_OK) rc = hip_err(hipEventElapsedTime(&t, ea, eb));
       if (rep > 0) tot += t;  // the first run warms up
     }
     if (rc != TOR_OK) break;
-    const double t = tot / 2.0;
+    const double t = tot / 2.0 * scale;
     if (ms) ms[sb - 1] = t;
     if (t < best_ms) {
       best_ms = t;
       best = sb;
     }
   }
+  (void)hipStreamSynchronize(s);
+  if (ea) (void)hipEventDestroy(ea);
+  if (eb) (void)hipEventDestroy(eb);
+  if (dres) (void)hipFree(dres);
   (void)hipFree(dO);
   if (rc != TOR_OK) return rc;
   {
@@ -1452,6 +1511,7 @@ int tor_autotune(int32_t n, int32_t tier, void* stream, int32_t* best_bottom, do
 
 int tor_autotune_save(const char* path) {
   if (!path) return TOR_EINVAL;
+  load_default_tune_table();
   FILE* f = fopen(path, "w");
   if (!f) return TOR_EINVAL;
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1460,6 +1520,15 @@ int tor_autotune_save(const char* path) {
 }
 
 int tor_autotune_load(const char* path) {
+  load_default_tune_table();  // a later load overrides the shipped table
+  return load_tune_table(path);
+}
+
+}  // extern "C"
+
+namespace tor {
+namespace {
+int load_tune_table(const char* path) {
   if (!path) return TOR_EINVAL;
   FILE* f = fopen(path, "r");
   if (!f) return TOR_EINVAL;
@@ -1475,6 +1544,10 @@ int tor_autotune_load(const char* path) {
   for (auto& kv : t) g_tuned[kv.first] = kv.second;
   return TOR_OK;
 }
+}  // namespace
+}  // namespace tor
+
+extern "C" {
 
 int tor_last_select_stats(tor_select_stats_t* o) {
   if (!o) return TOR_EINVAL;

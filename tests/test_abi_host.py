@@ -233,3 +233,41 @@ def test_batch_groups_stay_within_their_budget(L):
     assert L.tor_batch_workspace_bytes(12, 1, -1, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
     assert L.tor_batch_workspace_bytes(12, 9, 1, 0, ctypes.byref(b)) == _lib.TOR_EINVAL
     assert L.tor_batch_workspace_bytes(12, 1, 1, 0, None) == _lib.TOR_EINVAL
+
+
+def _workspace_in_subprocess(env_table, queries):
+    """tor_workspace_bytes(n, tier, 0) in a fresh process whose
+    TOR_AUTOTUNE_TABLE is env_table (None: unset)."""
+    import json
+    import subprocess
+    import sys
+    code = ("import json, sys; sys.path.insert(0, %r); import paper_2009_01177_amd as t; "
+            "print(json.dumps([t.tor_workspace_bytes(n, tier) for n, tier in %r]))" % (ROOT, queries))
+    env = dict(os.environ)
+    env.pop("TOR_AUTOTUNE_TABLE", None)
+    if env_table is not None:
+        env["TOR_AUTOTUNE_TABLE"] = env_table
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, check=True)
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def test_the_shipped_tuned_table_is_read_before_the_first_plan(tmp_path):
+    """Bottom sizes of data/autotune_default.txt are the library's defaults
+    in a fresh process (a plan's size shows its bottom size); a table named
+    by TOR_AUTOTUNE_TABLE replaces it, and an empty name reads none."""
+    import paper_2009_01177_amd as t
+    rows = [tuple(int(x) for x in ln.split()) for ln in
+            open(os.path.join(ROOT, "paper_2009_01177_amd", "data", "autotune_default.txt"))]
+    table = {(n, tier): sb for n, tier, sb in rows}
+    assert all((n, tier) in table for n in range(1, 41) for tier in (0, 1, 2))
+    names = {0: "fp64", 1: "dd", 2: "qd"}
+    picks = [(8, 1), (10, 0), (9, 2), (30, 1)]
+    got = _workspace_in_subprocess(None, [(n, names[tier]) for n, tier in picks])
+    for (n, tier), b in zip(picks, got):
+        assert b == t.tor_workspace_bytes(n, names[tier], table[(n, tier)]), (n, tier)
+    # another table
+    p = tmp_path / "tune.txt"
+    p.write_text("8 1 4\n")
+    assert _workspace_in_subprocess(str(p), [(8, "dd")]) == [t.tor_workspace_bytes(8, "dd", 4)]
+    # no table: the built-in choice (the largest bottom the tier compiles)
+    assert _workspace_in_subprocess("", [(8, "dd")]) == [t.tor_workspace_bytes(8, "dd", 5)]

@@ -126,10 +126,18 @@ def test_tiers_agree_on_the_n36_stress_workload(tor):
 
 
 def test_autotuner(tor, tmp_path):
+    # n = 20 is tuned as a batch group of 256 instances (the batched shape)
     best, ms = tor.tor_autotune(20, "dd")
     print(f"[large] autotune n=20 dd best={best} ms={ms}", flush=True)
     assert 1 <= best <= 5 and ms[best - 1] > 0
     assert ms[best - 1] == min(x for x in ms if x > 0)
+    # n = 46 on a share of its frontier, scaled to the whole evaluation
+    # (about 20 minutes in DD): seconds
+    import time
+    t = time.time()
+    b46, ms46 = tor.tor_autotune(46, "dd")
+    print(f"[large] autotune n=46 dd best={b46} in {time.time() - t:.1f} s, projected ms {ms46}", flush=True)
+    assert time.time() - t < 60 and 1 <= b46 <= 5 and ms46[b46 - 1] > 6e5
     p = str(tmp_path / "tune.txt")
     tor.tor_autotune_save(p)
     tor.tor_autotune_load(p)
