@@ -446,6 +446,40 @@ def n40_leg(tor):
     return out
 
 
+def large_leg(tor):
+    """Opt-in figures beyond the default legs: one quad-double evaluation of
+    the n = 30 workload, and parts of an n = 50 instance (the paper's
+    largest size) of the n = 40 workload's state (50 clicked modes): part 0
+    of 2^12 (2^38 subsets) in double-double and in binary64."""
+    import torch
+    import gbs_inputs as g
+    out = {}
+    O, _ = g.workload("n30_lossy")
+    Od = torch.from_numpy(O).to("cuda:0")
+    tor.tor_eval(Od, tier="qd")  # warm-up: workspace and code
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = tor.tor_eval(Od, tier="qd")
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    out["qd_n30"] = {"s": sec, "terms_per_s": float(1 << 30) / sec, "tor": r.value}
+    print(f"[bench] n=30 qd: {sec:.3f} s", file=sys.stderr, flush=True)
+    O, _ = g.workload("n40_lossy", n=50)
+    nparts = 1 << 12
+    for tier in ("fp64", "dd"):
+        tor.tor_eval_part(O, 1, nparts, tier=tier)  # warm-up: grows the workspace to the n = 50 plan
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = tor.tor_eval_part(O, 0, nparts, tier=tier)
+        sec = time.perf_counter() - t
+        terms = float(1 << 50) / nparts
+        out[f"n50_part_{tier}"] = {"part": 0, "nparts": nparts, "terms": terms, "s": sec,
+                                   "terms_per_s": terms / sec, "whole_instance_h": sec * nparts / 3600}
+        print(f"[bench] n=50 {tier} part of 2^38 subsets: {sec:.2f} s, {terms / sec:.3e} terms/s, "
+              f"whole instance {sec * nparts / 3600:.2f} h", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -474,6 +508,8 @@ def main():
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the n = 36 precision-stress leg (about 35 s: QD reference)")
     ap.add_argument("--no-n40", action="store_true", help="skip the n = 40 double-double leg (about 25 s)")
+    ap.add_argument("--large", action="store_true",
+                    help="add the quad-double n = 30 evaluation and n = 50 parts (about 20 s)")
     ap.add_argument("--mcmc-only", action="store_true",
                     help="run only the sampler leg and print its JSON object (for profiling)")
     ap.add_argument("--batch-only", action="store_true",
@@ -588,6 +624,8 @@ def main():
         line["stress_n36"] = stress_leg(tor)
     if not args.no_n40:
         line["n40"] = n40_leg(tor)
+    if args.large:
+        line["large"] = large_leg(tor)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(O, n, args.cpu_seconds)

@@ -194,9 +194,10 @@ int tor_combine_parts(int32_t tier, int32_t n, const tor_result_t* parts, int32_
  * sample of the network's FP64 and DD choices whose predicted error lies
  * within 4 decades of tau (1/32 of them, at least one per tier;
  * TOR_SPOT_FRACTION and TOR_SPOT_WINDOW override) is re-evaluated one tier
- * up; when a sample misses tau, every instance of that tier predicted at
- * least as hard is re-evaluated one tier up (tor_last_select_stats reports
- * the counts). */
+ * up within the same launch sequence (the re-evaluations join the groups
+ * of their n and tier); when a sample misses tau, every instance of that
+ * tier predicted at least as hard is re-evaluated one tier up
+ * (tor_last_select_stats reports the counts). */
 int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,
                      const int32_t* tiers, double tau, const tor_options_t* opt, void* stream,
                      tor_result_t* out);
@@ -324,9 +325,7 @@ int tor_autotune_load(const char* path);
  *   Top levels (their terms over the largest term, t_k = det(Q_kk)^(-1/2)
  *   for the level-(n-1) subset without mode k, t_kl likewise with the 4x4
  *   block of modes k, l for level n-2): f16 log mean_k t_k, f17 log max_k
- *   t_k, f18 log mean_{k<l} t_kl, f19 log max_{k<l} t_kl (0 when n = 1;
- *   NaN for n > 46, where Q does not fit in LDS beside R: such instances
- *   are outside any network's range and take the bound estimate).
+ *   t_k, f18 log mean_{k<l} t_kl, f19 log max_{k<l} t_kl (0 when n = 1).
  * Inputs as tor_eval_batched (offsets, n on the host); feats device,
  * batch x TOR_NFEAT.  Enqueued on `stream`. */
 int tor_features(const void* O_packed, const int64_t* offsets, const int32_t* n, int32_t batch,

@@ -619,7 +619,14 @@ int group_share(int tier, int n, int R, int sb) {
 // A batch grouped by (n, tier).
 struct BatchGroup {
   int n, tier;
-  std::vector<int32_t> idx;  // instance indices
+  std::vector<int32_t> idx;   // instance indices
+  std::vector<int32_t> slot;  // their result slots in the output array
+};
+
+// One evaluation of a batch call: instance k at `tier`, its result into
+// out[slot].  An instance may appear more than once (at different tiers).
+struct BatchItem {
+  int32_t k, tier, slot;
 };
 
 // Copy a plan into the shared plan buffer.  Earlier work on stream s may still
@@ -699,6 +706,8 @@ int ensure_aux(Workspace* w, size_t bytes, hipStream_t s) {
   if (w->aux) TOR_HIP(hipFree(w->aux));
   w->aux = nullptr;
   w->aux_cap = 0;
+  // captured graphs may write their results into the old buffer
+  drop_graphs(w);
   size_t cap = 1 << 20;
   while (cap < bytes) cap *= 2;
   TOR_HIP(hipMalloc((void**)&w->aux, cap));
@@ -706,22 +715,21 @@ int ensure_aux(Workspace* w, size_t bytes, hipStream_t s) {
   return TOR_OK;
 }
 
-// Evaluate the instances idx (indices into the batch arrays) at the tiers
-// tier_of[k] (no TOR_AUTO left), results to out[k].
+// Evaluate the items (instance indices into the batch arrays, tiers with no
+// TOR_AUTO left, result slots), results to out[slot].
 int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
-               const std::vector<int32_t>& idx, const std::vector<int32_t>& tier_of,
-               const tor_options_t* opt, tor_result_t* out, bool use_graph, hipStream_t s) {
+               const std::vector<BatchItem>& items, const tor_options_t* opt, tor_result_t* out,
+               bool use_graph, hipStream_t s) {
   std::string key;
   if (use_graph) {
     auto put = [&](const void* p, size_t b) { key.append((const char*)p, b); };
     put(&O_packed, sizeof(O_packed));
     put(&out, sizeof(out));
     put(&s, sizeof(s));
-    for (int32_t k : idx) {
-      put(&k, 4);
-      put(offsets + k, 8);
-      put(n + k, 4);
-      put(&tier_of[k], 4);
+    for (const BatchItem& it : items) {
+      put(&it, sizeof(it));
+      put(offsets + it.k, 8);
+      put(n + it.k, 4);
     }
     if (opt) put(opt, sizeof(*opt));
     auto it = w->graphs.find(key);
@@ -734,10 +742,10 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
   std::map<std::pair<int, int>, size_t> gmap;
   std::vector<BatchGroup> groups;
   std::vector<int32_t> triv_idx, triv_tier;
-  for (int32_t k : idx) {
-    const int t = tier_of[k];
+  for (const BatchItem& item : items) {
+    const int k = item.k, t = item.tier;
     if (n[k] == 0) {
-      triv_idx.push_back(k);
+      triv_idx.push_back(item.slot);
       triv_tier.push_back(t == TOR_AUTO ? TOR_FP64 : t);
       continue;
     }
@@ -746,10 +754,11 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
     auto it = gmap.find(key2);
     if (it == gmap.end()) {
       gmap[key2] = groups.size();
-      groups.push_back(BatchGroup{n[k], t, {}});
+      groups.push_back(BatchGroup{n[k], t, {}, {}});
       it = gmap.find(key2);
     }
     groups[it->second].idx.push_back(k);
+    groups[it->second].slot.push_back(item.slot);
   }
   // groups whose plan would outgrow the group budget run as several
   // sub-groups of equal size
@@ -760,8 +769,9 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
       const int R = (int)g.idx.size();
       const int per = group_share(g.tier, g.n, R, sb_opt);
       for (int a = 0; a < R; a += per) {
-        BatchGroup h{g.n, g.tier, {}};
+        BatchGroup h{g.n, g.tier, {}, {}};
         h.idx.assign(g.idx.begin() + a, g.idx.begin() + std::min(R, a + per));
+        h.slot.assign(g.slot.begin() + a, g.slot.begin() + std::min(R, a + per));
         split.push_back(std::move(h));
       }
     }
@@ -786,7 +796,7 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
       const int64_t o = offsets[k];
       meta.insert(meta.end(), (const char*)&o, (const char*)&o + 8);
     }
-    for (int32_t k : groups[gi].idx) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
+    for (int32_t k : groups[gi].slot) meta.insert(meta.end(), (const char*)&k, (const char*)&k + 4);
   }
   align8();
   const size_t triv_off = meta.size();
@@ -845,6 +855,16 @@ int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const
     sl->used = true;
   }
   return TOR_OK;
+}
+
+// The instances idx at the tiers tier_of[k], results to out[k].
+int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
+               const std::vector<int32_t>& idx, const std::vector<int32_t>& tier_of,
+               const tor_options_t* opt, tor_result_t* out, bool use_graph, hipStream_t s) {
+  std::vector<BatchItem> items;
+  items.reserve(idx.size());
+  for (int32_t k : idx) items.push_back(BatchItem{k, tier_of[k], k});
+  return batch_core(w, O_packed, offsets, n, items, opt, out, use_graph, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -977,15 +997,20 @@ int select_tiers(Workspace* w, const void* O_packed, const int64_t* offsets, con
   return TOR_OK;
 }
 
-// Spot re-evaluation of TOR_AUTO choices one tier up; escalate on a miss.
-// Only network choices whose predicted error lies within `window` decades
-// of tau are informative (a choice predicted far below tau cannot be
-// checked against tau by a re-evaluation that is itself only as good as the
-// next tier); a fraction of those is re-evaluated, at least one per tier.
-int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
-               int batch, const int32_t* tiers_req, double tau, std::vector<int32_t>& tier_of,
-               const std::vector<double>& pred, const std::vector<int32_t>& src, tor_result_t* out,
-               bool use_graph, hipStream_t s) {
+// Spot re-evaluation of TOR_AUTO choices one tier up.  Only network choices
+// whose predicted error lies within `window` decades of tau are informative
+// (a choice predicted far below tau cannot be checked against tau by a
+// re-evaluation that is itself only as good as the next tier); a fraction
+// of those is re-evaluated, at least one per tier.  The sample is drawn
+// before the evaluation so that its re-evaluations run in the same batch
+// (they join the groups of their n and tier, one launch sequence).
+struct SpotSample {
+  int32_t k, tier;  // instance, the tier it was chosen for
+};
+
+std::vector<SpotSample> spot_sample(int batch, const int32_t* n, const int32_t* tiers_req, double tau,
+                                    const std::vector<int32_t>& tier_of, const std::vector<double>& pred,
+                                    const std::vector<int32_t>& src) {
   double frac = 1.0 / 32.0;
   if (const char* e = getenv("TOR_SPOT_FRACTION")) {
     const double v = atof(e);
@@ -1003,62 +1028,56 @@ int spot_check(Workspace* w, const void* O_packed, const int64_t* offsets, const
   }
   const double ltau = log10(tau);
   const int stride = std::max(1, (int)llround(1.0 / frac));
-  int n_spot = 0, n_viol = 0, n_esc = 0;
+  std::vector<SpotSample> out;
   for (int t = TOR_FP64; t <= TOR_DD; ++t) {
-    std::vector<int32_t> cls, near;
-    for (int k = 0; k < batch; ++k) {
-      if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t) {
-        cls.push_back(k);
-        const double lerr = predicted_log10_err(sel, t, pred[k]);
-        if (src[k] == 0 && lerr >= ltau - window) near.push_back(k);
-      }
-    }
-    if (near.empty()) continue;
-    std::vector<int32_t> sample;
-    for (size_t i = 0; i < near.size(); i += stride) sample.push_back(near[i]);
-    n_spot += (int)sample.size();
-    // re-evaluate the sample one tier up into a scratch result array
-    const size_t rbytes = sizeof(tor_result_t) * batch;
-    TOR_TRY(ensure_aux(w, rbytes, s));
-    tor_result_t* scratch = (tor_result_t*)w->aux;
-    std::vector<int32_t> up(tier_of);
-    for (int32_t k : sample) up[k] = t + 1;
-    // the sample's evaluation is one more batch, replayed from the graph
-    // cache when the same batch comes again
-    tor_options_t gopt;
-    memset(&gopt, 0, sizeof(gopt));
-    gopt.flags = TOR_FLAG_GRAPH;
-    TOR_TRY(batch_core(w, O_packed, offsets, n, sample, up, use_graph ? &gopt : nullptr, scratch, use_graph, s));
-    std::vector<tor_result_t> hi(batch), lo(batch);
-    TOR_HIP(hipMemcpyAsync(hi.data(), scratch, rbytes, hipMemcpyDeviceToHost, s));
-    TOR_HIP(hipMemcpyAsync(lo.data(), out, rbytes, hipMemcpyDeviceToHost, s));
-    TOR_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> near;
+    for (int k = 0; k < batch; ++k)
+      if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t && src[k] == 0 &&
+          predicted_log10_err(sel, t, pred[k]) >= ltau - window)
+        near.push_back(k);
+    for (size_t i = 0; i < near.size(); i += stride) out.push_back(SpotSample{near[i], t});
+  }
+  return out;
+}
+
+// Compare each sampled result (res[k], chosen tier) with its re-evaluation
+// one tier up (res[batch + i]); on a miss, move up every instance of that
+// tier predicted at least as hard and evaluate those again into out.
+int spot_verify(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n, int batch,
+                const int32_t* tiers_req, double tau, std::vector<int32_t>& tier_of,
+                const std::vector<double>& pred, const std::vector<int32_t>& src,
+                const std::vector<SpotSample>& smp, const std::vector<tor_result_t>& res, tor_result_t* out,
+                hipStream_t s) {
+  int n_viol = 0, n_esc = 0;
+  for (int t = TOR_FP64; t <= TOR_DD; ++t) {
     double thr = 1e300;
     bool viol = false;
-    for (int32_t k : sample) {
-      const double th = hi[k].tor[0] + hi[k].tor[1];
-      const double tl = lo[k].tor[0] + lo[k].tor[1];
-      const double err = fabs(tl - th);
-      if (!(err <= tau * fabs(th))) {
+    for (size_t i = 0; i < smp.size(); ++i) {
+      if (smp[i].tier != t) continue;
+      const tor_result_t& hi = res[batch + i];
+      const tor_result_t& lo = res[smp[i].k];
+      const double th = hi.tor[0] + hi.tor[1];
+      const double tl = lo.tor[0] + lo.tor[1];
+      if (!(fabs(tl - th) <= tau * fabs(th))) {
         viol = true;
         ++n_viol;
-        thr = std::min(thr, pred[k]);
+        thr = std::min(thr, pred[smp[i].k]);
       }
     }
     if (!viol) continue;
-    // move up every instance of this tier predicted at least as hard
     std::vector<int32_t> esc;
-    for (int32_t k : cls)
-      if (pred[k] >= thr - 1.0 || src[k] == 1) esc.push_back(k);
+    for (int k = 0; k < batch; ++k)
+      if (n[k] > 0 && (tiers_req ? tiers_req[k] : TOR_AUTO) == TOR_AUTO && tier_of[k] == t &&
+          (pred[k] >= thr - 1.0 || src[k] == 1))
+        esc.push_back(k);
     for (int32_t k : esc) tier_of[k] = t + 1;
     n_esc += (int)esc.size();
     TOR_TRY(batch_core(w, O_packed, offsets, n, esc, tier_of, nullptr, out, false, s));
   }
   std::lock_guard<std::mutex> lk(g_sel_mu);
-  g_stats.n_spot = n_spot;
+  g_stats.n_spot = (int)smp.size();
   g_stats.n_violations = n_viol;
   g_stats.n_escalated = n_esc;
-  for (int k = 0; k < batch; ++k) (void)k;
   return TOR_OK;
 }
 
@@ -1328,12 +1347,31 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   if (any_auto) TOR_TRY(select_tiers(w, O_packed, offsets, n, batch, tau, tier_of.data(), &pred, &src, s));
 
   const bool use_graph = opt && (opt->flags & TOR_FLAG_GRAPH);
-  std::vector<int32_t> all(batch);
-  for (int k = 0; k < batch; ++k) all[k] = k;
-  TOR_TRY(batch_core(w, O_packed, offsets, n, all, tier_of, opt, out, use_graph, s));
-  if (any_auto)
-    TOR_TRY(spot_check(w, O_packed, offsets, n, batch, tiers, tau, tier_of, pred, src, out, use_graph, s));
-  return TOR_OK;
+  std::vector<BatchItem> items(batch);
+  for (int k = 0; k < batch; ++k) items[k] = BatchItem{k, tier_of[k], k};
+  std::vector<SpotSample> smp;
+  if (any_auto) smp = spot_sample(batch, n, tiers, tau, tier_of, pred, src);
+  if (smp.empty()) {
+    TOR_TRY(batch_core(w, O_packed, offsets, n, items, opt, out, use_graph, s));
+    if (any_auto) {
+      std::lock_guard<std::mutex> lk(g_sel_mu);
+      g_stats.n_spot = g_stats.n_violations = g_stats.n_escalated = 0;
+    }
+    return TOR_OK;
+  }
+  // the chosen tiers and the sample's re-evaluations one tier up in one
+  // batch, into a scratch result array: [0, batch) the batch, then the sample
+  const int total = batch + (int)smp.size();
+  for (size_t i = 0; i < smp.size(); ++i)
+    items.push_back(BatchItem{smp[i].k, smp[i].tier + 1, batch + (int32_t)i});
+  TOR_TRY(ensure_aux(w, sizeof(tor_result_t) * (size_t)total, s));
+  tor_result_t* res_dev = (tor_result_t*)w->aux;
+  TOR_TRY(batch_core(w, O_packed, offsets, n, items, opt, res_dev, use_graph, s));
+  TOR_HIP(hipMemcpyAsync(out, res_dev, sizeof(tor_result_t) * (size_t)batch, hipMemcpyDeviceToDevice, s));
+  std::vector<tor_result_t> res(total);
+  TOR_HIP(hipMemcpyAsync(res.data(), res_dev, sizeof(tor_result_t) * (size_t)total, hipMemcpyDeviceToHost, s));
+  TOR_HIP(hipStreamSynchronize(s));
+  return spot_verify(w, O_packed, offsets, n, batch, tiers, tau, tier_of, pred, src, smp, res, out, s);
 }
 
 int tor_mcmc(const void* O_full, int32_t M, int64_t ld, int32_t N, int32_t chains, int32_t steps,

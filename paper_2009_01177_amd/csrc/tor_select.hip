@@ -17,7 +17,7 @@ namespace tor {
 // --------------------------------------------------------------------------
 // Features (one workgroup of 256 threads per instance).  R is the real
 // quadrature form of I - O (rows interleaved per mode), full square in LDS;
-// Q = R^-1 (sigma_Q in the same basis) where it fits beside R.
+// Q = R^-1 (sigma_Q in the same basis) replaces it in the same array.
 //   f0  n
 //   f1  -1/2 log det(I - O)           (log of the largest term)
 //   f2  sum_k log((1 + q_k)/(1 - q_k)), q_k = det(I - O)_{kk}^(1/2)
@@ -49,48 +49,36 @@ __device__ inline double o_lower(const double2* O, int64_t ld, int r, int c, boo
   return imag ? -v.y : v.x;
 }
 
-__device__ inline double r_entry(const double2* O, int64_t ld, int n, int r, int c) {
-  const int i = r >> 1, j = c >> 1, qi = r & 1, qj = c & 1;
-  const double xr = o_lower(O, ld, i, j, false), xi = o_lower(O, ld, i, j, true);
-  const double yr = o_lower(O, ld, i, j + n, false), yi = o_lower(O, ld, i, j + n, true);
-  const double dlt = (i == j && qi == qj) ? 1.0 : 0.0;
-  if (qi == 0 && qj == 0) return (dlt - xr) - yr;
-  if (qi == 0 && qj == 1) return xi - yi;
-  if (qi == 1 && qj == 0) return -xi - yi;
-  return (dlt - xr) + yr;
+// Wavefront reductions by butterfly: lane results can differ in the last
+// bit for sums (each lane associates differently), so the sum is taken from
+// lane 0; min / max are exact in any order.
+__device__ inline double wave_sum(double x) {
+  for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+  return __shfl(x, 0);
+}
+__device__ inline double wave_min(double x) {
+  for (int o = 32; o >= 1; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ inline double wave_max(double x) {
+  for (int o = 32; o >= 1; o >>= 1) x = fmax(x, __shfl_xor(x, o));
+  return x;
+}
+__device__ inline int wave_min_int(int x) {
+  for (int o = 32; o >= 1; o >>= 1) x = min(x, __shfl_xor(x, o));
+  return x;
 }
 
-// det of the 4x4 symmetric block of modes (i, j) of a full N2 x N2 matrix,
-// by elimination without pivoting
-__device__ inline double det_pair(const double* R, int N2, int i, int j) {
-  int idx[4] = {2 * i, 2 * i + 1, 2 * j, 2 * j + 1};
-  double a[4][4];
-  for (int r = 0; r < 4; ++r)
-    for (int c = 0; c < 4; ++c) a[r][c] = R[idx[r] * N2 + idx[c]];
-  double det = 1.0;
-  for (int k = 0; k < 4; ++k) {
-    const double d = a[k][k];
-    det *= d;
-    for (int r = k + 1; r < 4; ++r) {
-      const double f = a[r][k] / d;
-      for (int c = k + 1; c < 4; ++c) a[r][c] -= f * a[k][c];
-    }
-  }
-  return det;
-}
-
-// sum of v[0..256) over the workgroup in a fixed order (every thread gets it)
-__device__ inline double block_sum(double x, double* red) {
-  const int tid = threadIdx.x;
-  red[tid] = x;
+// Sum over the workgroup's 256 threads in a fixed order (the four
+// wavefronts' sums, then (w0 + w1) + (w2 + w3)); every thread gets it.
+// red: 8 doubles of LDS, the two halves used alternately (`phase`), so one
+// barrier per call suffices as long as calls alternate phases.
+__device__ inline double block_sum(double x, double* red, int phase) {
+  const double ws = wave_sum(x);
+  double* r = red + 4 * phase;
+  if ((threadIdx.x & 63) == 0) r[threadIdx.x >> 6] = ws;
   __syncthreads();
-  for (int w = 128; w >= 1; w >>= 1) {
-    if (tid < w) red[tid] += red[tid + w];
-    __syncthreads();
-  }
-  const double v = red[0];
-  __syncthreads();
-  return v;
+  return (r[0] + r[1]) + (r[2] + r[3]);
 }
 
 // Number of eigenvalues below x of the k x k symmetric tridiagonal matrix
@@ -111,7 +99,7 @@ __device__ inline int sturm_count(const double* al, const double* be, int k, dou
 // inside its Gershgorin interval: in each round the 256 threads evaluate the
 // Sturm count at 256 interior points and the interval shrinks to the gap
 // where the count passes j (a factor of 257 per round).  Every thread
-// returns the same value.  cnt: 256 ints of LDS.
+// returns the same value.  cnt: 8 ints of LDS.
 __device__ inline double tridiag_eig(const double* al, const double* be, int k, int j, int* cnt) {
   const int tid = threadIdx.x;
   double lo = 1e300, hi = -1e300;
@@ -122,24 +110,61 @@ __device__ inline double tridiag_eig(const double* al, const double* be, int k, 
   }
   for (int round = 0; round < 8 && hi - lo > 1e-15 * fmax(fabs(lo), fabs(hi)); ++round) {
     const double w = (hi - lo) / 257.0;
-    cnt[tid] = sturm_count(al, be, k, lo + w * (tid + 1)) > j ? tid : 256;
+    const int m = wave_min_int(sturm_count(al, be, k, lo + w * (tid + 1)) > j ? tid : 256);
+    int* c = cnt + 4 * (round & 1);
+    if ((tid & 63) == 0) c[tid >> 6] = m;
     __syncthreads();
-    for (int h = 128; h >= 1; h >>= 1) {
-      if (tid < h) cnt[tid] = min(cnt[tid], cnt[tid + h]);
-      __syncthreads();
-    }
-    const int t = cnt[0];  // first point above eigenvalue j (256: none)
-    __syncthreads();
+    const int t = min(min(c[0], c[1]), min(c[2], c[3]));  // first point above eigenvalue j (256: none)
     const double nlo = lo + w * t, nhi = t < 256 ? lo + w * (t + 1) : hi;
     lo = nlo;
     hi = nhi;
   }
+  __syncthreads();  // cnt is free for the next call
   return 0.5 * (lo + hi);
+}
+
+// Row-major lower-triangle index e = r (r + 1) / 2 + c, c <= r  ->  (r, c).
+__device__ inline void tri_rc(int e, int* r, int* c) {
+  int rr = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+  while (rr * (rr + 1) / 2 > e) --rr;
+  while ((rr + 1) * (rr + 2) / 2 <= e) ++rr;
+  *r = rr;
+  *c = e - rr * (rr + 1) / 2;
+}
+
+// det of the 4x4 block of modes (i, j), i < j, of a symmetric matrix of
+// which only the lower triangle (with the diagonal) is stored
+__device__ inline double det_pair_lower(const double* A, int N2, int i, int j) {
+  const int idx[4] = {2 * i, 2 * i + 1, 2 * j, 2 * j + 1};
+  double a[4][4];
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) a[r][c] = r >= c ? A[idx[r] * N2 + idx[c]] : A[idx[c] * N2 + idx[r]];
+  double det = 1.0;
+  for (int k = 0; k < 4; ++k) {
+    const double d = a[k][k];
+    det *= d;
+    for (int r = k + 1; r < 4; ++r) {
+      const double f = a[r][k] / d;
+      for (int c = k + 1; c < 4; ++c) a[r][c] -= f * a[k][c];
+    }
+  }
+  return det;
+}
+
+// p -> (i, j), i < j, lexicographic over the n modes
+__device__ inline void pair_ij(int p, int n, int* i, int* j) {
+  int ii = 0, rem = p;
+  while (rem >= n - 1 - ii) {
+    rem -= n - 1 - ii;
+    ++ii;
+  }
+  *i = ii;
+  *j = ii + 1 + rem;
 }
 
 __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict__ Obase,
                                                        const int64_t* __restrict__ offs,
-                                                       const int32_t* __restrict__ ns, int nq,
+                                                       const int32_t* __restrict__ ns,
                                                        double* __restrict__ feats) {
   extern __shared__ double sh[];
   const int inst = blockIdx.x;
@@ -147,7 +172,7 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
   const int N2 = 2 * n;
   const int64_t ld = 2 * n;
   const double2* O = Obase + offs[inst];
-  double* R = sh;                   // N2 x N2
+  double* R = sh;                   // N2 x N2: R, then its factor, then Q (lower)
   double* piv = R + N2 * N2;        // N2
   double* q = piv + N2;             // n
   double* pr = q + n;               // 2 * npairs: log ratio, det^(-1/2)
@@ -158,10 +183,18 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
   double* al = lz + 3 * N2, *be = al + LANCZOS_STEPS;
   double* gl = be + LANCZOS_STEPS;  // Gershgorin per row: lo, hi (N2 each)
   double* tq = gl + 2 * N2;         // n + npairs: det(Q_k)^(-1/2), then det(Q_kl)^(-1/2)
-  double* Q = tq + n + npairs;      // N2 x N2 (instances of up to nq modes)
-  const bool with_q = n <= nq;
   const int tid = threadIdx.x;
-  for (int e = tid; e < N2 * N2; e += 256) R[e] = r_entry(O, ld, n, e / N2, e % N2);
+  // R, one mode pair (its 2 x 2 block, four reads of O) per thread
+  for (int pp = tid; pp < n * n; pp += 256) {
+    const int i = pp / n, j = pp - (pp / n) * n;
+    const double xr = o_lower(O, ld, i, j, false), xi = o_lower(O, ld, i, j, true);
+    const double yr = o_lower(O, ld, i, j + n, false), yi = o_lower(O, ld, i, j + n, true);
+    const double dlt = i == j ? 1.0 : 0.0;
+    R[(2 * i) * N2 + 2 * j] = (dlt - xr) - yr;
+    R[(2 * i) * N2 + 2 * j + 1] = xi - yi;
+    R[(2 * i + 1) * N2 + 2 * j] = -xi - yi;
+    R[(2 * i + 1) * N2 + 2 * j + 1] = (dlt - xr) + yr;
+  }
   __syncthreads();
   for (int k = tid; k < n; k += 256) {
     const double d = R[(2 * k) * N2 + 2 * k] * R[(2 * k + 1) * N2 + 2 * k + 1] -
@@ -178,14 +211,9 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
   }
   __syncthreads();
   for (int p = tid; p < npairs; p += 256) {
-    // p -> (i, j), i < j, lexicographic
-    int i = 0, rem = p;
-    while (rem >= n - 1 - i) {
-      rem -= n - 1 - i;
-      ++i;
-    }
-    const int j = i + 1 + rem;
-    const double dij = det_pair(R, N2, i, j);
+    int i, j;
+    pair_ij(p, n, &i, &j);
+    const double dij = det_pair_lower(R, N2, i, j);
     pr[2 * p] = log(dij / (q[i] * q[i] * q[j] * q[j]));
     pr[2 * p + 1] = 1.0 / sqrt(dij);
   }
@@ -197,15 +225,32 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
     vc[r] = 1.0 / sqrt((double)N2);
   }
   __syncthreads();
+  // w = R v in nsplit column slices (thread (slice, row)), the slices'
+  // partial products in red[8..) summed in slice order per row
+  const int nsplit = N2 <= 62 ? 4 : (N2 <= 82 ? 3 : 2);
+  double* mv = red + 8;
+  const int mrow = tid % N2, mpart = tid / N2;
+  const int mc0 = mpart * N2 / nsplit, mc1 = (mpart + 1) * N2 / nsplit;
   for (int j = 0; j < ksteps; ++j) {
+    if (mpart < nsplit) {
+      double s0 = 0.0, s1 = 0.0;
+      int c = mc0;
+      for (; c + 1 < mc1; c += 2) {
+        s0 = fma(R[mrow * N2 + c], vc[c], s0);
+        s1 = fma(R[mrow * N2 + c + 1], vc[c + 1], s1);
+      }
+      if (c < mc1) s0 = fma(R[mrow * N2 + c], vc[c], s0);
+      mv[mpart * N2 + mrow] = s0 + s1;
+    }
+    __syncthreads();
     double part = 0.0;
     for (int r = tid; r < N2; r += 256) {
-      double s = 0.0;
-      for (int c = 0; c < N2; ++c) s = fma(R[r * N2 + c], vc[c], s);
-      wv[r] = s;
-      part = fma(s, vc[r], part);
+      double sr = mv[r];
+      for (int q2 = 1; q2 < nsplit; ++q2) sr += mv[q2 * N2 + r];
+      wv[r] = sr;
+      part = fma(sr, vc[r], part);
     }
-    const double a = block_sum(part, red);
+    const double a = block_sum(part, red, 0);
     const double bprev = j > 0 ? be[j - 1] : 0.0;
     part = 0.0;
     for (int r = tid; r < N2; r += 256) {
@@ -213,7 +258,7 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
       wv[r] = w;
       part = fma(w, w, part);
     }
-    const double b = sqrt(block_sum(part, red));
+    const double b = sqrt(block_sum(part, red, 1));
     if (tid == 0) {
       al[j] = a;
       be[j] = b;
@@ -227,87 +272,150 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
     __syncthreads();
   }
   __syncthreads();
-  // Cholesky of R in place, unscaled (R = L D L^T: piv = D, the eliminated
-  // column below the pivot is D_j L_rj)
+  // Cholesky of R in place, lower triangle, unscaled (R = L D L^T: piv = D,
+  // the eliminated column below the pivot is D_j L_rj).  Step j updates the
+  // triangle of rows and columns > j, four entries per thread per pass with
+  // their loads issued first (column j is not written in step j, so it is
+  // read without a barrier before the update).
   for (int j = 0; j < N2; ++j) {
     const double d = R[j * N2 + j];
     if (tid == 0) piv[j] = d;
-    __syncthreads();
     const double rd = 1.0 / d;
-    for (int e = tid; e < (N2 - j - 1) * (N2 - j - 1); e += 256) {
-      const int r = j + 1 + e / (N2 - j - 1), c = j + 1 + e % (N2 - j - 1);
-      if (c <= r) R[r * N2 + c] -= R[r * N2 + j] * R[c * N2 + j] * rd;
+    const int m = N2 - j - 1, cnt = m * (m + 1) / 2;
+    for (int e0 = tid; e0 < cnt; e0 += 1024) {
+      int ro[4], co[4];
+      double t[4], x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < cnt) {
+          tri_rc(e, &ro[u], &co[u]);
+          ro[u] += j + 1;
+          co[u] += j + 1;
+          x[u] = R[ro[u] * N2 + j];
+          y[u] = R[co[u] * N2 + j];
+          t[u] = R[ro[u] * N2 + co[u]];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + 256 * u < cnt) R[ro[u] * N2 + co[u]] = t[u] - x[u] * y[u] * rd;
     }
     __syncthreads();
   }
-  // Q = R^-1, one column per thread: L y = e_c, then L^T x = D^-1 y, with
-  // the unit lower factor L formed in place first (column j of the
-  // eliminated part over its pivot) and the pivots' reciprocals kept in wv
-  if (with_q) {
-    for (int j = tid; j < N2; j += 256) wv[j] = 1.0 / piv[j];
-    __syncthreads();
-    for (int e = tid; e < N2 * N2; e += 256) {
-      const int r = e / N2, c = e - r * N2;
-      if (r > c) R[e] *= wv[c];
-    }
-    __syncthreads();
-    for (int c = tid; c < N2; c += 256) {
-      double* x = Q;  // column c of Q: Q[i * N2 + c]
-      for (int i = 0; i < N2; ++i) {
-        double y = (i == c) ? 1.0 : 0.0;
-        for (int j = c; j < i; ++j) y = fma(-R[i * N2 + j], x[j * N2 + c], y);
-        x[i * N2 + c] = i < c ? 0.0 : y;
+  // Q = R^-1 = X^T D^-1 X with X = L^-1 (unit lower), in R's own array:
+  // the unit factor L formed in the lower triangle (column j of the
+  // eliminated part over its pivot; reciprocal pivots in wv), X below its
+  // unit diagonal kept transposed in the upper triangle (X_ic at (c, i)),
+  // built by right-looking elimination (step j subtracts L_ij times row j
+  // of X from every row i > j), then Q into the lower triangle and the
+  // diagonal
+  for (int j = tid; j < N2; j += 256) wv[j] = 1.0 / piv[j];
+  __syncthreads();
+  for (int e = tid; e < N2 * N2; e += 256) {
+    const int r = e / N2, c = e - (e / N2) * N2;
+    if (r > c) R[e] *= wv[c];
+    if (r < c) R[e] = 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j + 1 < N2; ++j) {
+    // (i, c), j < i < N2, 0 <= c <= j: X_ic -= L_ij X_jc (X_jj = 1)
+    const int w = j + 1, cnt = (N2 - 1 - j) * w;
+    for (int e0 = tid; e0 < cnt; e0 += 1024) {
+      int io[4], co[4];
+      double t[4], l[4], xj[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + 256 * u;
+        if (e < cnt) {
+          io[u] = j + 1 + e / w;
+          co[u] = e - (e / w) * w;
+          l[u] = R[io[u] * N2 + j];
+          xj[u] = co[u] == j ? 1.0 : R[co[u] * N2 + j];
+          t[u] = R[co[u] * N2 + io[u]];
+        }
       }
-      for (int i = N2 - 1; i >= 0; --i) {
-        double z = x[i * N2 + c] * wv[i];
-        for (int j = i + 1; j < N2; ++j) z = fma(-R[j * N2 + i], x[j * N2 + c], z);
-        x[i * N2 + c] = z;
-      }
-    }
-    __syncthreads();
-    // the top levels' term ratios, one mode or pair per thread
-    for (int k = tid; k < n; k += 256) {
-      const double* Qk = Q + (2 * k) * N2 + 2 * k;
-      tq[k] = 1.0 / sqrt(Qk[0] * Qk[N2 + 1] - Qk[N2] * Qk[N2]);
-    }
-    for (int p = tid; p < npairs; p += 256) {
-      int i = 0, rem = p;
-      while (rem >= n - 1 - i) {
-        rem -= n - 1 - i;
-        ++i;
-      }
-      tq[n + p] = 1.0 / sqrt(det_pair(Q, N2, i, i + 1 + rem));
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (e0 + 256 * u < cnt) R[co[u] * N2 + io[u]] = t[u] - l[u] * xj[u];
     }
     __syncthreads();
   }
+  // Q_ab = sum_{k >= a} X_ka X_kb / d_k for a >= b (X_ka = 0 for k < a):
+  // reads the upper triangle only, writes the lower one and the diagonal
+  for (int e = tid; e < N2 * (N2 + 1) / 2; e += 256) {
+    int a, b;
+    tri_rc(e, &a, &b);
+    double s0 = (a == b ? 1.0 : R[b * N2 + a]) * wv[a], s1 = 0.0;
+    int k = a + 1;
+    for (; k + 1 < N2; k += 2) {
+      s0 = fma(R[a * N2 + k] * wv[k], R[b * N2 + k], s0);
+      s1 = fma(R[a * N2 + k + 1] * wv[k + 1], R[b * N2 + k + 1], s1);
+    }
+    if (k < N2) s0 = fma(R[a * N2 + k] * wv[k], R[b * N2 + k], s0);
+    R[a * N2 + b] = s0 + s1;
+  }
+  __syncthreads();
+  // the top levels' term ratios, one mode or pair per thread
+  for (int k = tid; k < n; k += 256) {
+    const double* Qk = R + (2 * k) * N2 + 2 * k;
+    tq[k] = 1.0 / sqrt(Qk[0] * Qk[N2 + 1] - Qk[N2] * Qk[N2]);
+  }
+  for (int p = tid; p < npairs; p += 256) {
+    int i, j;
+    pair_ij(p, n, &i, &j);
+    tq[n + p] = 1.0 / sqrt(det_pair_lower(R, N2, i, j));
+  }
+  __syncthreads();
   // extreme Ritz values (all threads take part in the multisection)
   const double ritz_lo = tridiag_eig(al, be, kdone, 0, (int*)red);
   const double ritz_hi = tridiag_eig(al, be, kdone, kdone - 1, (int*)red);
+  // the rest: per-thread partial sums, minima and maxima, then per
+  // wavefront, then the four wavefronts in a fixed order
+  const double inf = __builtin_inf();
+  double sm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // logdet f2 f3 asum f6 pt s1 s2
+  double mn[3] = {inf, inf, inf};                           // pmin qmin glo
+  double mx[5] = {-inf, -inf, -inf, 0.0, 0.0};              // pmax qmax ghi m1 m2
+  for (int j = tid; j < N2; j += 256) {
+    sm[0] += log(piv[j]);
+    mn[0] = fmin(mn[0], piv[j]);
+    mx[0] = fmax(mx[0], piv[j]);
+    mn[2] = fmin(mn[2], gl[j]);
+    mx[2] = fmax(mx[2], gl[N2 + j]);
+  }
+  for (int k = tid; k < n; k += 256) {
+    sm[1] += log((1.0 + q[k]) / (1.0 - q[k]));
+    sm[2] += -log(q[k]);
+    sm[3] += O[(int64_t)k * ld + k].x;
+    mn[1] = fmin(mn[1], q[k]);
+    mx[1] = fmax(mx[1], q[k]);
+    sm[6] += tq[k];
+    mx[3] = fmax(mx[3], tq[k]);
+  }
+  for (int p = tid; p < npairs; p += 256) {
+    sm[4] += pr[2 * p];
+    sm[5] += pr[2 * p + 1];
+    sm[7] += tq[n + p];
+    mx[4] = fmax(mx[4], tq[n + p]);
+  }
+  double* wr = red + 16 * (tid >> 6);
+  {
+    double v[16];
+    for (int i = 0; i < 8; ++i) v[i] = wave_sum(sm[i]);
+    for (int i = 0; i < 3; ++i) v[8 + i] = wave_min(mn[i]);
+    for (int i = 0; i < 5; ++i) v[11 + i] = wave_max(mx[i]);
+    if ((tid & 63) == 0)
+      for (int i = 0; i < 16; ++i) wr[i] = v[i];
+  }
+  __syncthreads();
   if (tid == 0) {
-    double logdet = 0.0, pmin = piv[0], pmax = piv[0];
-    for (int j = 0; j < N2; ++j) {
-      logdet += log(piv[j]);
-      pmin = fmin(pmin, piv[j]);
-      pmax = fmax(pmax, piv[j]);
-    }
-    double f2 = 0.0, f3 = 0.0, qmax = q[0], qmin = q[0], asum = 0.0;
-    for (int k = 0; k < n; ++k) {
-      f2 += log((1.0 + q[k]) / (1.0 - q[k]));
-      f3 += -log(q[k]);
-      qmax = fmax(qmax, q[k]);
-      qmin = fmin(qmin, q[k]);
-      asum += O[(int64_t)k * ld + k].x;
-    }
-    double f6 = 0.0, pt = 0.0;
-    for (int p = 0; p < npairs; ++p) {
-      f6 += pr[2 * p];
-      pt += pr[2 * p + 1];
-    }
-    double glo = gl[0], ghi = gl[N2];
-    for (int r = 1; r < N2; ++r) {
-      glo = fmin(glo, gl[r]);
-      ghi = fmax(ghi, gl[N2 + r]);
-    }
+    double v[16];
+    for (int i = 0; i < 8; ++i) v[i] = (red[i] + red[16 + i]) + (red[32 + i] + red[48 + i]);
+    for (int i = 8; i < 11; ++i) v[i] = fmin(fmin(red[i], red[16 + i]), fmin(red[32 + i], red[48 + i]));
+    for (int i = 11; i < 16; ++i) v[i] = fmax(fmax(red[i], red[16 + i]), fmax(red[32 + i], red[48 + i]));
+    const double logdet = v[0], f2 = v[1], f3 = v[2], asum = v[3], f6 = v[4], pt = v[5], s1 = v[6], s2 = v[7];
+    const double pmin = v[8], qmin = v[9], glo = v[10];
+    const double pmax = v[11], qmax = v[12], ghi = v[13], m1 = v[14], m2 = v[15];
     const double a = asum / n;
     double* f = feats + (size_t)inst * TOR_NFEAT;
     f[0] = n;
@@ -326,50 +434,19 @@ __global__ __launch_bounds__(256) void features_kernel(const double2* __restrict
     f[13] = log(ghi);
     f[14] = log(ritz_lo);
     f[15] = log(ritz_hi);
-    if (with_q) {
-      double s1 = 0.0, m1 = 0.0;
-      for (int k = 0; k < n; ++k) {
-        s1 += tq[k];
-        m1 = fmax(m1, tq[k]);
-      }
-      double s2 = 0.0, m2 = 0.0;
-      for (int p = 0; p < npairs; ++p) {
-        s2 += tq[n + p];
-        m2 = fmax(m2, tq[n + p]);
-      }
-      f[16] = log(s1 / n);
-      f[17] = log(m1);
-      f[18] = npairs > 0 ? log(s2 / npairs) : 0.0;
-      f[19] = npairs > 0 ? log(m2) : 0.0;
-    } else {
-      const double nan = __builtin_nan("");
-      f[16] = f[17] = f[18] = f[19] = nan;
-    }
+    f[16] = log(s1 / n);
+    f[17] = log(m1);
+    f[18] = npairs > 0 ? log(s2 / npairs) : 0.0;
+    f[19] = npairs > 0 ? log(m2) : 0.0;
   }
 }
 
-// LDS of the features kernel for instances of up to nmax modes, with or
-// without the inverse Q.
-size_t features_lds_bytes(int nmax, bool with_q) {
-  const size_t N2 = 2 * (size_t)nmax;
-  const size_t base = N2 * N2 + N2 + nmax + (size_t)nmax * (nmax - 1) + 256 + 3 * N2 + 2 * LANCZOS_STEPS + 2 * N2 +
-                      nmax + (size_t)nmax * (nmax - 1) / 2;
-  return sizeof(double) * (base + (with_q ? N2 * N2 : 0));
-}
-
-constexpr size_t FEATURES_LDS_MAX = 160 * 1024;
-
-// Largest n whose instances get Q beside R (the top-level features f16..f19).
-int features_nq() {
-  int nq = 0;
-  while (nq < TOR_NMAX && features_lds_bytes(nq + 1, true) <= FEATURES_LDS_MAX) ++nq;
-  return nq;
-}
-
+// LDS of the features kernel for instances of up to nmax modes (R and its
+// inverse share one N2 x N2 array: every n up to TOR_NMAX fits).
 size_t features_lds_bytes(int nmax) {
-  const int nq = features_nq();
-  const size_t a = features_lds_bytes(nmax < nq ? nmax : nq, true), b = features_lds_bytes(nmax, false);
-  return a > b ? a : b;
+  const size_t N2 = 2 * (size_t)nmax;
+  return sizeof(double) * (N2 * N2 + N2 + nmax + (size_t)nmax * (nmax - 1) + 256 + 3 * N2 +
+                           2 * LANCZOS_STEPS + 2 * N2 + nmax + (size_t)nmax * (nmax - 1) / 2);
 }
 
 hipError_t launch_features(const double2* O, const int64_t* offs, const int32_t* ns, int batch,
@@ -379,7 +456,7 @@ hipError_t launch_features(const double2* O, const int64_t* offs, const int32_t*
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&features_kernel),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(features_kernel, dim3(batch), dim3(256), lds, s, O, offs, ns, features_nq(), feats);
+  hipLaunchKernelGGL(features_kernel, dim3(batch), dim3(256), lds, s, O, offs, ns, feats);
   return hipGetLastError();
 }
 

@@ -32,17 +32,15 @@ def test_features_kernel_matches_reference(tor):
         assert np.allclose(f[k], want, rtol=1e-10, atol=1e-10), (k, f[k] - want)
 
 
-def test_features_beyond_the_inverse_limit(tor):
-    """From n = 47 the inverse does not fit beside R in LDS: the top-level
-    features are NaN (the bound estimate decides for such instances), the
-    others still match the reference; a small instance in the same launch
-    keeps all of its features."""
-    Os = [g.random_instance(47, 77), g.random_instance(9, 78)]
+def test_features_at_the_largest_n(tor):
+    """R and its inverse share one array in LDS, so every feature is
+    defined up to n = TOR_NMAX; instances of 47 and 50 modes match the
+    reference, and a small instance in the same launch keeps its features."""
+    Os = [g.random_instance(47, 77), g.random_instance(9, 78), g.random_instance(50, 79)]
     f = tor.tor_features(tor.Batch(Os)).cpu().numpy()
-    want = ref.features(Os[0])
-    assert np.all(np.isnan(f[0, 16:]))
-    assert np.allclose(f[0, :16], want[:16], rtol=1e-10, atol=1e-10)
-    assert np.allclose(f[1], ref.features(Os[1]), rtol=1e-10, atol=1e-10)
+    for k in range(3):
+        assert np.all(np.isfinite(f[k]))
+        assert np.allclose(f[k], ref.features(Os[k]), rtol=1e-10, atol=1e-10), (k, f[k] - ref.features(Os[k]))
 
 
 def test_mlp_kernels_match_reference(tor):
