@@ -227,6 +227,50 @@ def test_spot_check_escalates_a_wrong_choice(tor, trained):
     assert not _meets(res, _reference_qd(tor, Os), 1e-6)
 
 
+def test_spot_samples_ride_in_the_batch(tor, trained):
+    """Every network choice sampled (TOR_SPOT_FRACTION = 1, a wide window):
+    the re-evaluations one tier up run in the batch's own launch sequence,
+    into slots after the batch's.  Each instance's result (fixed tiers, n = 0
+    and TOR_AUTO mixed) is its own evaluation at the tier it reports, within
+    that tier's tolerance of S_abs; graph replays give the same bits."""
+    _, _, _, path = trained
+    tor.tor_selector_load(path)
+    Os = [O for O in g.batched_workload(batch=200) if 6 <= O.shape[0] // 2 <= 16][:48]
+    Os = Os[:20] + [np.zeros((0, 0), dtype=np.complex128)] + Os[20:]
+    tiers = ["auto"] * len(Os)
+    tiers[3], tiers[7], tiers[30] = "dd", "fp64", "qd"
+    b = tor.Batch(Os)
+    old = {k: os.environ.get(k) for k in ("TOR_SPOT_FRACTION", "TOR_SPOT_WINDOW")}
+    os.environ["TOR_SPOT_FRACTION"] = "1"
+    os.environ["TOR_SPOT_WINDOW"] = "100"
+    try:
+        res = tor.tor_eval_batched(b, tiers=tiers, tau=1e-3)
+        st = tor.tor_last_select_stats()
+        again = tor.tor_eval_batched(b, tiers=tiers, tau=1e-3, graph=True)
+        again = tor.tor_eval_batched(b, tiers=tiers, tau=1e-3, graph=True)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    print(f"[spot] {st}", flush=True)
+    _, _, src = tor.tor_select_tiers(b, 1e-3)
+    n_net = sum(1 for k, O in enumerate(Os) if tiers[k] == "auto" and O.shape[0] > 0 and src[k] == 0)
+    assert n_net > 0 and st["n_spot"] == n_net
+    assert st["n_violations"] > 0 or st["n_escalated"] == 0
+    tol = {0: 1e-12, 1: 1e-25, 2: 1e-30}
+    for k, (O, r) in enumerate(zip(Os, res)):
+        if O.shape[0] == 0:
+            assert r.exact == 1
+            continue
+        if tiers[k] != "auto":
+            assert r.tier_used == tor.tier_id(tiers[k])
+        one = tor.tor_eval(O, tier=r.tier_used)
+        assert abs(r.exact - one.exact) <= tol[r.tier_used] * one.abs_exact, k
+    assert [(r.expansion, r.tier_used) for r in again] == [(r.expansion, r.tier_used) for r in res]
+
+
 @pytest.mark.parametrize("learned", [False, True])
 def test_auto_graph_replays_survive_spot_checks(tor, trained, learned):
     """Regression: TOR_AUTO with graph capture, called repeatedly.  Each call
