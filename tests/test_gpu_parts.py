@@ -116,7 +116,7 @@ def test_interrupted_run_resumes_from_its_checkpoint(tor, tmp_path):
     assert float(abs(total.exact - whole.exact) / whole.abs_exact) <= 1e-25
 
 
-def _share_against_the_oracle(tor, O, code, k, tiers=("dd", "fp64")):
+def _share_against_the_oracle(tor, O, code, k, tiers=("dd", "fp64", "qd")):
     """The share `code` of 2^k of instance O through the timed kernels (the
     default bottom sizes and launch shape) against the binary128 oracle's
     terms for exactly the subsets whose decisions on modes 0..k-1 spell
