@@ -480,6 +480,38 @@ def large_leg(tor):
     return out
 
 
+def phase_leg(tor, steps: int):
+    """Where the middle + bottom kernel's time goes, from the phase-clock
+    build (per wavefront, shader-clock cycles between marks in the kernel):
+    the n = 30 workload in DD and FP64, per middle state and as fractions
+    of the wavefronts' time."""
+    import torch
+    import gbs_inputs as g
+    O, _ = g.workload("n30_lossy")
+    Od = torch.from_numpy(O).to("cuda:0")
+    n = O.shape[0] // 2
+    out = {}
+    for tier in ("dd", "fp64"):
+        tor.tor_eval(Od, tier=tier, algo="schur")
+        torch.cuda.synchronize()
+        tor.tor_debug_phase_clocks(reset=True)
+        kms = 0.0
+        for _ in range(steps):
+            tor.tor_eval(Od, tier=tier, algo="schur", time_kernel=True)
+            k, d_used, grid, launches = tor.tor_last_kernel_ms()
+            kms += k
+        ph = tor.tor_debug_phase_clocks(reset=True)
+        states = steps * (1 << d_used)
+        tot = sum(ph.values())
+        out[tier] = {"middle_states": states, "kernel_ms": kms, "grid": grid,
+                     "cycles_per_state": {k: v / states for k, v in ph.items()},
+                     "fraction": {k: v / tot for k, v in ph.items()},
+                     "wave_cycles_per_kernel_s": tot / (kms / 1e3)}
+        print(f"[bench] phases {tier}: " + " ".join(f"{k}={v / states:.0f}" for k, v in ph.items())
+              + f" cycles per middle state ({steps} evaluations, {states} states)", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,6 +540,8 @@ def main():
     ap.add_argument("--no-stress", action="store_true",
                     help="skip the n = 36 precision-stress leg (about 35 s: QD reference)")
     ap.add_argument("--no-n40", action="store_true", help="skip the n = 40 double-double leg (about 25 s)")
+    ap.add_argument("--phase-clocks", action="store_true",
+                    help="only the per-phase clocks of the middle + bottom kernel (loads the phase-clock build)")
     ap.add_argument("--large", action="store_true",
                     help="add the quad-double n = 30 evaluation and n = 50 parts (about 20 s)")
     ap.add_argument("--mcmc-only", action="store_true",
@@ -525,10 +559,15 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    if args.phase_clocks:
+        os.environ.setdefault("TOR_LIBRARY", os.path.join(ROOT, "paper_2009_01177_amd", "libtor_hip_phase.so"))
     import numpy as np
     import torch
     import gbs_inputs as g
     import paper_2009_01177_amd as tor
+    if args.phase_clocks:
+        print(json.dumps({"phase_clocks": phase_leg(tor, max(args.steps, 1))}), flush=True)
+        return
 
     if args.copy_calibration > 0:
         src = torch.ones(args.copy_calibration, dtype=torch.uint8, device="cuda:0")

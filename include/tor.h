@@ -44,7 +44,7 @@ extern "C" {
 #define TOR_ENOTPD (-2)       /* a pivot was not > 0: I - O is not positive definite */
 #define TOR_EHIP (-3)         /* a HIP runtime error */
 #define TOR_ENOMEM (-4)       /* device allocation failed */
-#define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan */
+#define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan, or the build lacks the facility */
 
 /* Largest n accepted: the paper's largest instance (N = 50, a 100 x 100
  * matrix, Sec. 7).  Subset masks are 64-bit.  The Schur path keeps a
@@ -255,6 +255,23 @@ int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, voi
  * tor_debug_level_sums, any n up to TOR_NMAX.  Synchronous. */
 int tor_debug_level_sums_schur(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,
                                double* out_levels, tor_result_t* out);
+
+/* Where the middle + bottom kernel's time goes: the shader-clock cycles its
+ * wavefronts spent in each phase, summed over all wavefronts since the last
+ * reset, TOR_NPHASE values in this order: the expansion's middle levels in
+ * LDS (with the next state's prefetch), each lane's own last middle level,
+ * the barrier after the expansion, the bottom level, the wave totals and
+ * the partial's store, the barrier after the bottom, set-up and tail.  The
+ * paper times its elimination kernels the same way, per kernel and per
+ * instruction schedule (Sec. 6, Table 3).  Only a library built with
+ * TOR_PHASE_CLOCKS counts (the in-tree build writes it beside the regular
+ * one, as libtor_hip_phase.so); the regular library answers
+ * TOR_EUNSUPPORTED.
+ *   reset  nonzero: zero the totals after reading them
+ *   out    host, TOR_NPHASE uint64
+ * Reads the current device's totals; synchronous. */
+#define TOR_NPHASE 7
+int tor_debug_phase_clocks(int32_t reset, uint64_t* out);
 
 /* det(I - O_Z)^(-1/2) with its sign (-1)^(n-|Z|) for k explicit subsets
  * (one term of Eq. 2 each).

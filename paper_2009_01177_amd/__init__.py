@@ -7,7 +7,7 @@ the library; the first call does, and raises if it is missing.
 from ._lib import TorError, TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO  # noqa: F401
 from .api import (  # noqa: F401
     TorResult, Batch, tor_eval_batched, tor_version, tor_init, tor_shutdown, tor_eval, tor_debug_level_sums,
-    tor_debug_sampled_terms, tor_last_kernel_ms, tor_next_mask, tor_kth_mask, tor_plan_items,
+    tor_debug_sampled_terms, tor_debug_phase_clocks, tor_last_kernel_ms, tor_next_mask, tor_kth_mask, tor_plan_items,
     tor_features, tor_mlp_forward, tor_mlp_grad, tor_mlp_adam, tor_selector_set, tor_selector_get,
     tor_selector_save, tor_selector_load, tor_fallback_bits, tor_select_tiers, tor_last_select_stats,
     tor_autotune, tor_autotune_save, tor_autotune_load, tor_mcmc, results_of, tier_id,

@@ -10,7 +10,11 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
+# The regular in-tree build.  TOR_LIBRARY, read when the library is first
+# loaded, selects another build of it (the phase-clock build,
+# libtor_hip_phase.so).
 LIB_PATH = os.path.join(HERE, "libtor_hip.so")
+TOR_NPHASE = 7
 
 TOR_OK, TOR_EINVAL, TOR_ENOTPD, TOR_EHIP, TOR_ENOMEM, TOR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO = 0, 1, 2, -1
@@ -32,6 +36,7 @@ EXPORTS = (
     "tor_autotune", "tor_autotune_save", "tor_autotune_load", "tor_workspace_bytes",
     "tor_batch_workspace_bytes", "tor_eval_noalloc", "tor_noalloc_nmax",
     "tor_mlp_grad_quantile", "tor_selector_label", "tor_selector_train", "tor_debug_level_sums_schur",
+    "tor_debug_phase_clocks",
 )
 
 TOR_NFEAT = 20
@@ -139,12 +144,13 @@ def lib():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
+    path = os.environ.get("TOR_LIBRARY") or LIB_PATH
+    if not os.path.exists(path):
         raise ImportError(
-            "libtor_hip.so is not built (run `python -m paper_2009_01177_amd.build` "
+            f"{path} is not built (run `python -m paper_2009_01177_amd.build` "
             "or __graft_entry__.build())")
     _torch_gpu_first()
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
     dp = ctypes.POINTER(ctypes.c_double)
     L.tor_version.restype = ctypes.c_char_p
@@ -171,6 +177,8 @@ def lib():
     L.tor_debug_level_sums.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
     L.tor_debug_level_sums_schur.restype = ctypes.c_int
     L.tor_debug_level_sums_schur.argtypes = [vp, i32, i64, i32, vp, dp, ctypes.POINTER(TorResultC)]
+    L.tor_debug_phase_clocks.restype = ctypes.c_int
+    L.tor_debug_phase_clocks.argtypes = [i32, ctypes.POINTER(u64)]
     L.tor_debug_sampled_terms.restype = ctypes.c_int
     L.tor_debug_sampled_terms.argtypes = [vp, i32, i64, i32, vp, i64, vp, vp]
     L.tor_last_kernel_ms.restype = ctypes.c_double

@@ -415,6 +415,18 @@ def tor_debug_level_sums(O, tier="dd", stream=None, algo="border"):
     return levels, _res(out)
 
 
+PHASES = ("expand", "last_level", "wait_after_expand", "bottom", "totals", "wait_after_bottom", "other")
+
+
+def tor_debug_phase_clocks(reset: bool = False) -> dict:
+    """Shader-clock cycles of the middle + bottom kernel per phase, summed
+    over its wavefronts (include/tor.h, tor_debug_phase_clocks); needs the
+    phase-clock build (TOR_LIBRARY=.../libtor_hip_phase.so)."""
+    out = (ctypes.c_uint64 * _lib.TOR_NPHASE)()
+    check(lib().tor_debug_phase_clocks(1 if reset else 0, out), "tor_debug_phase_clocks")
+    return {name: int(out[k]) for k, name in enumerate(PHASES)}
+
+
 def tor_debug_sampled_terms(O, masks, tier="dd", stream=None) -> np.ndarray:
     """Signed terms of the given subsets: array (k, 4) of expansions."""
     torch = _torch()

@@ -49,20 +49,30 @@ def _run(cmd, verbose):
     return subprocess.run(cmd, capture_output=True, text=True)
 
 
+PHASE_LIB = os.path.join(HERE, "libtor_hip_phase.so")
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     """Compile every source to an object (in parallel, one hipcc per
     source: each object carries its own gfx950 code), then link the shared
-    library."""
-    if not force and up_to_date():
+    library.  The Schur kernels are compiled a second time with their
+    per-phase clocks (TOR_PHASE_CLOCKS) and linked with the same other
+    objects into libtor_hip_phase.so, which tor_debug_phase_clocks reads
+    (load it with TOR_LIBRARY)."""
+    if not force and up_to_date() and os.path.exists(PHASE_LIB):
         return LIB
     from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     os.makedirs(OBJ_DIR, exist_ok=True)
     cflags = [f for f in FLAGS if f != "-shared"]
+    inc = ["-I", os.path.join(ROOT, "include")]
     jobs = []
     for src in sources():
         obj = os.path.join(OBJ_DIR, os.path.basename(src) + ".o")
-        jobs.append((obj, [hipcc] + cflags + ["-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]))
+        jobs.append((obj, [hipcc] + cflags + inc + ["-c", src, "-o", obj]))
+    schur = os.path.join(CSRC, "tor_schur.hip")
+    phase_obj = os.path.join(OBJ_DIR, "tor_schur_phase.o")
+    jobs.append((phase_obj, [hipcc] + cflags + ["-DTOR_PHASE_CLOCKS"] + inc + ["-c", schur, "-o", phase_obj]))
     workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4))))
     with ThreadPoolExecutor(workers) as ex:
         results = list(ex.map(lambda j: _run(j[1], verbose), jobs))
@@ -70,15 +80,19 @@ def build(force: bool = True, verbose: bool = False) -> str:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError("hipcc failed (%d) on %s" % (r.returncode, cmd[-3]))
-    tmp = LIB + ".tmp%d" % os.getpid()
-    r = _run([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + [o for o, _ in jobs], verbose)
-    if r.returncode != 0:
-        sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc link failed (%d)" % r.returncode)
-    os.replace(tmp, LIB)
+    main_objs = [o for o, _ in jobs if o != phase_obj]
+    phase_objs = [phase_obj] + [o for o in main_objs if not o.endswith("tor_schur.hip.o")]
+    for out, objs in ((LIB, main_objs), (PHASE_LIB, phase_objs)):
+        tmp = out + ".tmp%d" % os.getpid()
+        r = _run([hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs, verbose)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc link failed (%d)" % r.returncode)
+        os.replace(tmp, out)
     return LIB
 
 
 if __name__ == "__main__":
-    build(force="--force" in sys.argv or True, verbose=True)
+    build(force=True, verbose=True)
     print(LIB)
+    print(PHASE_LIB)

@@ -1113,7 +1113,7 @@ const char* tor_strerror(int code) {
     case TOR_ENOTPD: return "I - O is not positive definite (a pivot was not > 0)";
     case TOR_EHIP: return "HIP runtime error";
     case TOR_ENOMEM: return "device allocation failed";
-    case TOR_EUNSUPPORTED: return "tier and n do not fit the kernel's storage plan";
+    case TOR_EUNSUPPORTED: return "not supported: tier and n do not fit the kernel's storage plan, or this build lacks the facility";
     default: return "unknown error";
   }
 }
@@ -1779,6 +1779,14 @@ int tor_debug_level_sums(const void* O, int32_t n, int64_t ld, int32_t tier, voi
     for (int k = 0; k < 4; ++k) out_levels[4 * m + k] = v.x[k];
   }
   return out->status;
+}
+
+int tor_debug_phase_clocks(int32_t reset, uint64_t* out) {
+  if (!out) return TOR_EINVAL;
+  const hipError_t e = phase_clocks(reset != 0, out);
+  if (e == hipErrorNotSupported) return TOR_EUNSUPPORTED;
+  TOR_HIP(e);
+  return TOR_OK;
 }
 
 int tor_debug_level_sums_schur(const void* O, int32_t n, int64_t ld, int32_t tier, void* stream,

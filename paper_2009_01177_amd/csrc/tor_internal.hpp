@@ -105,6 +105,10 @@ hipError_t leaf_levels_occupancy(int tier, int s_b, int* blocks_per_cu);
 hipError_t launch_leaf(int tier, int s_m, int s_b, const void* mat, const void* g, const int32_t* m,
                        int nst, int n, void* partials, int32_t* status, int grid, hipStream_t st);
 hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu);
+// The middle + bottom kernel's per-phase clock totals (TOR_NPHASE values;
+// reset: zero them after reading).  hipErrorNotSupported unless the kernels
+// were built with TOR_PHASE_CLOCKS.
+hipError_t phase_clocks(bool reset, uint64_t* out);
 
 // ---- selector kernels (tor_select.hip) ----
 size_t features_lds_bytes(int nmax);

@@ -55,6 +55,46 @@ __host__ __device__ constexpr int psize(int s) { return s * (2 * s + 1); }
 // different states hit different banks.
 __host__ __device__ constexpr int odd_up(int v) { return v | 1; }
 
+// Per-phase clocks of the middle + bottom kernel (a build with
+// TOR_PHASE_CLOCKS defined; otherwise PhaseClock is empty and every mark
+// compiles to nothing).  Each wavefront adds the shader-clock cycles between
+// consecutive marks to the phase the interval belongs to, and at its end
+// adds its totals into tor_phase_clk, one atomic per phase.
+enum LeafPhase : int {
+  PH_EXPAND = 0,  // store, prefetch and the middle levels in LDS
+  PH_LAST = 1,    // each lane's own last middle level, in registers
+  PH_WAIT_A = 2,  // the barrier after the expansion
+  PH_BOTTOM = 3,  // the bottom level, in registers
+  PH_TOTALS = 4,  // the wave's fixed-order totals and the partial's store
+  PH_WAIT_B = 5,  // the barrier after the bottom
+  PH_OTHER = 6,   // set-up and the tail
+  PH_COUNT = 7
+};
+#ifdef TOR_PHASE_CLOCKS
+__device__ unsigned long long tor_phase_clk[PH_COUNT];
+struct PhaseClock {
+  unsigned long long acc[PH_COUNT];
+  unsigned long long t;
+  __device__ PhaseClock() : t(clock64()) {
+    for (int k = 0; k < PH_COUNT; ++k) acc[k] = 0;
+  }
+  __device__ __forceinline__ void mark(int k) {
+    const unsigned long long u = clock64();
+    acc[k] += u - t;
+    t = u;
+  }
+  __device__ void flush(int lane) {
+    if (lane == 0)
+      for (int k = 0; k < PH_COUNT; ++k) atomicAdd(&tor_phase_clk[k], acc[k]);
+  }
+};
+#else
+struct PhaseClock {
+  __device__ __forceinline__ void mark(int) {}
+  __device__ __forceinline__ void flush(int) {}
+};
+#endif
+
 // --------------------------------------------------------------------------
 // Real-tier arithmetic helpers
 // --------------------------------------------------------------------------
@@ -727,7 +767,7 @@ struct Leaf {
   __device__ __forceinline__ static void expand(SMEM& sm, const R* mat, const R* gin, const int32_t* min_,
                                                 int zn, int nstates, int s_m, int L, int ps0, int lane,
                                                 bool& bad, R& v0, R& v1, R& v2, R& v3, R& v4, R& v5, R& g, int32_t& m,
-                                                R (&leaf)[psize(SB)], R& lg, int32_t& lm) {
+                                                R (&leaf)[psize(SB)], R& lg, int32_t& lm, PhaseClock& pc) {
     store(sm, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
     if (zn < nstates) fetch(mat, gin, min_, zn, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
     wave_sync();
@@ -735,15 +775,18 @@ struct Leaf {
     R* cg;
     int32_t* cm;
     middle(sm, s_m, L, lane, bad, cur, cg, cm);
+    pc.mark(PH_EXPAND);
     if (L == 0) {
 #pragma unroll
       for (int e = 0; e < psize(SB); ++e) leaf[e] = cur[e];
       lg = cg[0];
       lm = cm[0];
+      pc.mark(PH_LAST);
       return;
     }
     const int zz = lane < (1 << L) ? lane >> 1 : 0;
     last_level(cur + zz * odd_up(psize(SB + 1)), cg[zz], cm[zz], L, lane, bad, leaf, lg, lm);
+    pc.mark(PH_LAST);
   }
 
   // The same, but the lane's pair state (all of it: lane 0 takes the whole
@@ -809,7 +852,7 @@ struct Leaf {
   // them into its level sums lvs[0..n] (LDS) lane by lane in lane order.
   template <bool LV = false>
   __device__ __forceinline__ static void finish(const R (&leaf)[psize(SB)], const R& lg, int32_t lm, int L,
-                                                int lane, int n, int z, Acc* partials, bool& bad,
+                                                int lane, int n, int z, Acc* partials, bool& bad, PhaseClock& pc,
                                                 Acc* lvs = nullptr) {
     LaneAcc<TT, LV ? SB + 1 : 0> acc;
     acc.p[0] = TT::acc_zero();
@@ -819,6 +862,7 @@ struct Leaf {
       for (int d = 0; d <= SB; ++d) acc.lv[d] = TT::acc_zero();
     }
     if (lane < (1 << L)) Bottom<TT, SB>::template run<0>(leaf, lg, acc, bad);
+    pc.mark(PH_BOTTOM);
     if constexpr (LV) {
       for (int l = 0; l < (1 << L); ++l) {
         const int ml = __builtin_amdgcn_readlane(lm, l);
@@ -839,6 +883,7 @@ struct Leaf {
       partials[(size_t)z * 2] = tt;
       partials[(size_t)z * 2 + 1] = ta;
     }
+    pc.mark(PH_TOTALS);
   }
 };
 
@@ -910,6 +955,7 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
   R leaf[psize(SB)];
   R P[LF::NP];
 
+  PhaseClock pc;
   const int zb = W * (int)blockIdx.x;
   if (zb + wv < nstates) LF::fetch(mat, gin, min_, zb + wv, ps0, lane, v0, v1, v2, v3, v4, v5, g, m);
   // W = 2: both wavefronts run the same loop, expand | barrier | bottom |
@@ -919,28 +965,38 @@ __attribute__((amdgpu_waves_per_eu(leaf_waves_per_simd<TT, SB, W>()))) void leaf
   // expansion.  Both run 2 * rounds + 1 barriers.
   const int rounds = zb < nstates ? (nstates - zb + zstride - 1) / zstride : 0;
   if (W == 2 && wv == 1) __syncthreads();
+  pc.mark(PH_OTHER);
   for (int t = 0; t < rounds; ++t) {
     const int z = zb + wv + t * zstride;
     if (z < nstates) {
-      if constexpr (PR)
+      if constexpr (PR) {
         LF::expand_pair(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, v4, v5, g,
                         m, P, pg, pm);
-      else
+        pc.mark(PH_EXPAND);
+      } else {
         LF::expand(sm, mat, gin, min_, z + zstride, nstates, s_m, L, ps0, lane, bad, v0, v1, v2, v3, v4, v5, g, m,
-                   leaf, lg, lm);
+                   leaf, lg, lm, pc);
+      }
     }
     if (W == 2) __syncthreads(); else wave_sync();
+    pc.mark(PH_WAIT_A);
     if (z < nstates) {
-      if constexpr (PR) LF::last_level(P, pg, pm, L, lane, bad, leaf, lg, lm);
-      LF::template finish<LV>(leaf, lg, lm, L, lane, n, z, partials, bad, lvs);
+      if constexpr (PR) {
+        LF::last_level(P, pg, pm, L, lane, bad, leaf, lg, lm);
+        pc.mark(PH_LAST);
+      }
+      LF::template finish<LV>(leaf, lg, lm, L, lane, n, z, partials, bad, pc, lvs);
     }
     if (W == 2) __syncthreads();
+    pc.mark(PH_WAIT_B);
   }
   if (W == 2 && wv == 0) __syncthreads();
   if constexpr (LV) {
     wave_sync();
     for (int m = lane; m <= n; m += 64) lvpart[(size_t)blockIdx.x * (n + 1) + m] = lvs[m];
   }
+  pc.mark(PH_OTHER);
+  pc.flush(lane);
   if (bad) atomicOr(status, 1);
 }
 
@@ -1176,5 +1232,24 @@ hipError_t leaf_occupancy(int tier, int s_b, int* blocks_per_cu) {
 #undef CALL
 }
 #undef TOR_LEAF_DISPATCH
+
+hipError_t phase_clocks(bool reset, uint64_t* out) {
+#ifdef TOR_PHASE_CLOCKS
+  static_assert(PH_COUNT == TOR_NPHASE, "phase count");
+  unsigned long long h[PH_COUNT];
+  hipError_t e = hipMemcpyFromSymbol(h, HIP_SYMBOL(tor_phase_clk), sizeof(h), 0, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < PH_COUNT; ++k) out[k] = h[k];
+  if (reset) {
+    const unsigned long long zero[PH_COUNT] = {};
+    e = hipMemcpyToSymbol(HIP_SYMBOL(tor_phase_clk), zero, sizeof(zero), 0, hipMemcpyHostToDevice);
+  }
+  return e;
+#else
+  (void)reset;
+  (void)out;
+  return hipErrorNotSupported;
+#endif
+}
 
 }  // namespace tor

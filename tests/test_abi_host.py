@@ -69,6 +69,18 @@ def test_plan_covers_every_prefix_once_largest_first(n, d):
     assert pops == sorted(pops, reverse=True)
 
 
+def test_phase_clocks_only_in_the_phase_build(L):
+    """The regular library has no per-phase clocks and says so; the build
+    writes the phase-clock library beside it."""
+    from paper_2009_01177_amd import _lib, build
+    out = (ctypes.c_uint64 * _lib.TOR_NPHASE)()
+    assert L.tor_debug_phase_clocks(0, out) == _lib.TOR_EUNSUPPORTED
+    assert L.tor_debug_phase_clocks(0, None) == _lib.TOR_EINVAL
+    assert os.path.exists(build.PHASE_LIB)
+    P = ctypes.CDLL(build.PHASE_LIB)
+    assert P.tor_debug_phase_clocks(0, None) == _lib.TOR_EINVAL
+
+
 def test_argument_checks_need_no_gpu(L):
     from paper_2009_01177_amd import _lib
     out = _lib.TorResultC()
