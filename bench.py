@@ -554,7 +554,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build evaluates a Torontonian on a single "
+        print("bench.py measures one GPU only: the library evaluates a Torontonian on a single "
               "MI355X (--gpus 1); multi-GPU sharding of the subset tree is not implemented.",
               file=sys.stderr)
         sys.exit(2)

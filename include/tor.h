@@ -44,7 +44,7 @@ extern "C" {
 #define TOR_ENOTPD (-2)       /* a pivot was not > 0: I - O is not positive definite */
 #define TOR_EHIP (-3)         /* a HIP runtime error */
 #define TOR_ENOMEM (-4)       /* device allocation failed */
-#define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan, or the build lacks the facility */
+#define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan, or the library was compiled without the facility */
 
 /* Largest n accepted: the paper's largest instance (N = 50, a 100 x 100
  * matrix, Sec. 7).  Subset masks are 64-bit.  The Schur path keeps a

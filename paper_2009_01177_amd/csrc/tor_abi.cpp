@@ -1113,7 +1113,7 @@ const char* tor_strerror(int code) {
     case TOR_ENOTPD: return "I - O is not positive definite (a pivot was not > 0)";
     case TOR_EHIP: return "HIP runtime error";
     case TOR_ENOMEM: return "device allocation failed";
-    case TOR_EUNSUPPORTED: return "not supported: tier and n do not fit the kernel's storage plan, or this build lacks the facility";
+    case TOR_EUNSUPPORTED: return "not supported: tier and n do not fit the kernel's storage plan, or the library was compiled without this facility";
     default: return "unknown error";
   }
 }

@@ -70,7 +70,7 @@ def test_plan_covers_every_prefix_once_largest_first(n, d):
 
 
 def test_phase_clocks_only_in_the_phase_build(L):
-    """The regular library has no per-phase clocks and says so; the build
+    """The regular library has no per-phase clocks and says so; build.py
     writes the phase-clock library beside it."""
     from paper_2009_01177_amd import _lib, build
     out = (ctypes.c_uint64 * _lib.TOR_NPHASE)()
