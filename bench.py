@@ -483,15 +483,15 @@ def large_leg(tor):
 def phase_leg(tor, steps: int):
     """Where the middle + bottom kernel's time goes, from the phase-clock
     build (per wavefront, shader-clock cycles between marks in the kernel):
-    the n = 30 workload in DD and FP64, per middle state and as fractions
-    of the wavefronts' time."""
+    the n = 30 workload in DD, FP64 and QD, per middle state and as
+    fractions of the wavefronts' time."""
     import torch
     import gbs_inputs as g
     O, _ = g.workload("n30_lossy")
     Od = torch.from_numpy(O).to("cuda:0")
     n = O.shape[0] // 2
     out = {}
-    for tier in ("dd", "fp64"):
+    for tier in ("dd", "fp64", "qd"):
         tor.tor_eval(Od, tier=tier, algo="schur")
         torch.cuda.synchronize()
         tor.tor_debug_phase_clocks(reset=True)
