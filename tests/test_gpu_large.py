@@ -115,6 +115,20 @@ def test_extreme_level_sums_through_the_schur_kernels(tor, name, ms, tier, tol):
     assert res.status == 0
 
 
+def test_extreme_level_sums_at_n30_in_quad_double(tor):
+    """The same P14 check in quad-double (bottoms of at most two modes in the
+    level-sum mode), held to the binary128 oracle's own accuracy."""
+    name, ms = "n30_lossy", [0, 1, 2, 3, 4, 26, 27, 28, 29, 30]
+    O, _ = g.workload(name)
+    print(f"[large] {name} level sums {ms} via schur, tier=qd", flush=True)
+    levels, res = tor.tor_debug_level_sums(O, tier="qd", algo="schur")
+    if name not in _ORACLE_LEVELS:
+        _ORACLE_LEVELS[name] = oracle.level_sums(O, ms)
+    for m, w in zip(ms, _ORACLE_LEVELS[name]):
+        assert float(abs(levels[m] - w) / w) <= 1e-30, m
+    assert res.status == 0
+
+
 def test_tiers_agree_on_the_n30_workload(tor):
     """FP64 and DD against QD on the benchmark's own instance (kappa 2.6e21)."""
     O, _ = g.workload("n30_lossy")
