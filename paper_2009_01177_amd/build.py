@@ -89,7 +89,30 @@ def build(force: bool = True, verbose: bool = False) -> str:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError("hipcc link failed (%d)" % r.returncode)
         os.replace(tmp, out)
+    build_c_client(verbose)
     return LIB
+
+
+C_CLIENT = os.path.join(ROOT, "tests", "c_client", "tor_client")
+
+
+def build_c_client(verbose: bool = False) -> str:
+    """The plain C client of the ABI that the tests run (gcc, no Python or
+    PyTorch): linked against the in-tree libtor_hip.so, found at run time
+    relative to the binary."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    src = C_CLIENT + ".c"
+    tmp = C_CLIENT + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
+           "-I", os.path.join(ROOT, "include"), src, "-L", HERE, "-ltor_hip", "-L", os.path.join(rocm, "lib"),
+           "-lamdhip64", "-Wl,-rpath,$ORIGIN/../../paper_2009_01177_amd", "-Wl,-rpath," + os.path.join(rocm, "lib"),
+           "-o", tmp]
+    r = _run(cmd, verbose)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("gcc failed (%d) on %s" % (r.returncode, src))
+    os.replace(tmp, C_CLIENT)
+    return C_CLIENT
 
 
 if __name__ == "__main__":

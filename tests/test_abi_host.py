@@ -81,6 +81,18 @@ def test_phase_clocks_only_in_the_phase_build(L):
     assert P.tor_debug_phase_clocks(0, None) == _lib.TOR_EINVAL
 
 
+def test_c_client_links_and_checks_its_arguments_without_a_gpu():
+    """The plain C client of the ABI is built, resolves libtor_hip.so from
+    the tree, and rejects a bad call before touching a device."""
+    import subprocess
+    from paper_2009_01177_amd import build
+    assert os.path.exists(build.C_CLIENT)
+    p = subprocess.run([build.C_CLIENT], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 1 and "usage" in p.stderr
+    p = subprocess.run([build.C_CLIENT, "/nonexistent", "3"], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 1 and "cannot read" in p.stderr
+
+
 def test_argument_checks_need_no_gpu(L):
     from paper_2009_01177_amd import _lib
     out = _lib.TorResultC()
