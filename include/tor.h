@@ -45,6 +45,7 @@ extern "C" {
 #define TOR_EHIP (-3)         /* a HIP runtime error */
 #define TOR_ENOMEM (-4)       /* device allocation failed */
 #define TOR_EUNSUPPORTED (-5) /* tier x n does not fit the kernel's storage plan, or the library was compiled without the facility */
+#define TOR_EINPUT (-6)       /* TOR_FLAG_CHECK_INPUT: O is not finite, not Hermitian, or lacks the block structure of Eq. 3 */
 
 /* Largest n accepted: the paper's largest instance (N = 50, a 100 x 100
  * matrix, Sec. 7).  Subset masks are 64-bit.  The Schur path keeps a
@@ -110,6 +111,14 @@ typedef struct tor_options {
  * use and replay it when the same batch (same pointers, sizes, offsets and
  * tiers) comes again. */
 #define TOR_FLAG_GRAPH 2
+/* tor_eval, tor_eval_part, tor_eval_batched: first check on the device that
+ * every O is what the kernels assume (they read the lower triangle and the
+ * O00 / O01 blocks only): all entries finite, O Hermitian, O11 = conj(O00)
+ * and O10 = conj(O01) (the block structure of the sampling matrix, Eq. 3),
+ * compared exactly.  On a violation the call evaluates nothing and returns
+ * TOR_EINPUT.  The check is one small kernel and a copy of one flag per
+ * instance, synchronous; without the flag nothing is checked. */
+#define TOR_FLAG_CHECK_INPUT 4
 
 /* Library version string. */
 const char* tor_version(void);

@@ -17,11 +17,13 @@ LIB_PATH = os.path.join(HERE, "libtor_hip.so")
 TOR_NPHASE = 7
 
 TOR_OK, TOR_EINVAL, TOR_ENOTPD, TOR_EHIP, TOR_ENOMEM, TOR_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+TOR_EINPUT = -6
 TOR_FP64, TOR_DD, TOR_QD, TOR_AUTO = 0, 1, 2, -1
 TOR_ALGO_AUTO, TOR_ALGO_BORDER, TOR_ALGO_SCHUR = 0, 1, 2
 TOR_NMAX = 50
 TOR_FLAG_TIME_KERNEL = 1
 TOR_FLAG_GRAPH = 2
+TOR_FLAG_CHECK_INPUT = 4
 TOR_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 # Every symbol include/tor.h declares.

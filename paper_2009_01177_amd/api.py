@@ -106,10 +106,10 @@ def tor_shutdown():
 
 def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
              stream=None, raise_on_error: bool = True, time_kernel: bool = False,
-             bottom_modes: int = 0) -> TorResult:
-    """Tor(O) of one instance (synchronous)."""
+             bottom_modes: int = 0, check_input: bool = False) -> TorResult:
+    """Tor(O) of one instance (synchronous); check_input: TOR_FLAG_CHECK_INPUT."""
     Od, n, ld = _device_o(O)
-    flags = _lib.TOR_FLAG_TIME_KERNEL if time_kernel else 0
+    flags = (_lib.TOR_FLAG_TIME_KERNEL if time_kernel else 0) | (_lib.TOR_FLAG_CHECK_INPUT if check_input else 0)
     opt = _lib.TorOptionsC(algo_id(algo), int(split_depth), int(grid), flags, int(bottom_modes))
     out = _lib.TorResultC()
     rc = lib().tor_eval(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), ctypes.byref(opt),
@@ -120,10 +120,11 @@ def tor_eval(O, tier="dd", algo="auto", split_depth: int = -1, grid: int = 0,
 
 
 def tor_eval_part(O, part: int, nparts: int, tier="dd", stream=None, bottom_modes: int = 0,
-                  raise_on_error: bool = True) -> TorResult:
+                  raise_on_error: bool = True, check_input: bool = False) -> TorResult:
     """Share `part` of `nparts` of Tor(O) (include/tor.h, tor_eval_part)."""
     Od, n, ld = _device_o(O)
-    opt = _lib.TorOptionsC(_lib.TOR_ALGO_AUTO, -1, 0, 0, int(bottom_modes))
+    opt = _lib.TorOptionsC(_lib.TOR_ALGO_AUTO, -1, 0, _lib.TOR_FLAG_CHECK_INPUT if check_input else 0,
+                           int(bottom_modes))
     out = _lib.TorResultC()
     rc = lib().tor_eval_part(ctypes.c_void_p(Od.data_ptr()), n, ld, tier_id(tier), ctypes.byref(opt),
                              _stream_ptr(stream), int(part), int(nparts), ctypes.byref(out))
@@ -176,7 +177,7 @@ def _results_from(buf):
 
 
 def tor_eval_batched(batch: "Batch", tiers=None, tau: float = 1e-3, graph: bool = False,
-                     stream=None, bottom_modes: int = 0, sync: bool = True):
+                     stream=None, bottom_modes: int = 0, sync: bool = True, check_input: bool = False):
     """Torontonians of a packed batch; returns a list of TorResult when
     sync is True (else None: the results are in batch.out on the device)."""
     torch = _torch()
@@ -188,7 +189,7 @@ def tor_eval_batched(batch: "Batch", tiers=None, tau: float = 1e-3, graph: bool 
             tiers = [tiers] * B
         t = np.ascontiguousarray([tier_id(x) for x in tiers], dtype=np.int32)
         tptr = t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
-    flags = _lib.TOR_FLAG_GRAPH if graph else 0
+    flags = (_lib.TOR_FLAG_GRAPH if graph else 0) | (_lib.TOR_FLAG_CHECK_INPUT if check_input else 0)
     opt = _lib.TorOptionsC(_lib.TOR_ALGO_AUTO, -1, 0, flags, int(bottom_modes))
     rc = lib().tor_eval_batched(ctypes.c_void_p(batch.O.data_ptr()),
                                 batch.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),

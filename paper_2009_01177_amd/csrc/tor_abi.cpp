@@ -715,6 +715,45 @@ int ensure_aux(Workspace* w, size_t bytes, hipStream_t s) {
   return TOR_OK;
 }
 
+// TOR_FLAG_CHECK_INPUT: the input conventions of the instances with n > 0,
+// checked on the device (one flag per instance, copied back); TOR_EINPUT if
+// any is violated.  offsets == nullptr: the single instance O (n, ld).
+int check_input(Workspace* w, const void* O, const int64_t* offsets, const int32_t* n, int count, int32_t n1,
+                int64_t ld1, hipStream_t s) {
+  std::vector<int64_t> off;
+  std::vector<int32_t> nn;
+  if (offsets) {
+    for (int k = 0; k < count; ++k)
+      if (n[k] > 0) {
+        off.push_back(offsets[k]);
+        nn.push_back(n[k]);
+      }
+  }
+  const int m = offsets ? (int)off.size() : (n1 > 0 ? 1 : 0);
+  if (m == 0) return TOR_OK;
+  const size_t o_off = ((size_t)4 * m + 7) & ~(size_t)7, o_n = o_off + (size_t)8 * m;
+  TOR_TRY(ensure_aux(w, o_n + (size_t)4 * m, s));
+  int32_t* bad = (int32_t*)w->aux;
+  const int64_t* d_off = nullptr;
+  const int32_t* d_n = nullptr;
+  if (offsets) {
+    TOR_HIP(hipMemcpyAsync(w->aux + o_off, off.data(), (size_t)8 * m, hipMemcpyHostToDevice, s));
+    TOR_HIP(hipMemcpyAsync(w->aux + o_n, nn.data(), (size_t)4 * m, hipMemcpyHostToDevice, s));
+    d_off = (const int64_t*)(w->aux + o_off);
+    d_n = (const int32_t*)(w->aux + o_n);
+  }
+  TOR_HIP(launch_zero_words((uint32_t*)bad, m, s));
+  TOR_HIP(launch_check_input((const double2*)O, d_off, d_n, m, n1, ld1, bad, s));
+  std::vector<int32_t> h(m);
+  TOR_HIP(hipMemcpyAsync(h.data(), bad, (size_t)4 * m, hipMemcpyDeviceToHost, s));
+  TOR_HIP(hipStreamSynchronize(s));
+  for (int32_t v : h)
+    if (v) return TOR_EINPUT;
+  return TOR_OK;
+}
+
+bool wants_check(const tor_options_t* opt) { return opt && (opt->flags & TOR_FLAG_CHECK_INPUT); }
+
 // Evaluate the items (instance indices into the batch arrays, tiers with no
 // TOR_AUTO left, result slots), results to out[slot].
 int batch_core(Workspace* w, const void* O_packed, const int64_t* offsets, const int32_t* n,
@@ -1113,6 +1152,7 @@ const char* tor_strerror(int code) {
     case TOR_ENOTPD: return "I - O is not positive definite (a pivot was not > 0)";
     case TOR_EHIP: return "HIP runtime error";
     case TOR_ENOMEM: return "device allocation failed";
+    case TOR_EINPUT: return "O is not finite, not Hermitian, or lacks the block structure of Eq. 3";
     case TOR_EUNSUPPORTED: return "not supported: tier and n do not fit the kernel's storage plan, or the library was compiled without this facility";
     default: return "unknown error";
   }
@@ -1168,6 +1208,7 @@ int tor_eval(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_optio
   Workspace* w = nullptr;
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
+  if (wants_check(opt)) TOR_TRY(check_input(w, O, nullptr, nullptr, 1, n, ld, s));
   RunOut ro;
   const int algo = opt ? opt->algo : TOR_ALGO_AUTO;
   if (algo != TOR_ALGO_AUTO && algo != TOR_ALGO_BORDER && algo != TOR_ALGO_SCHUR) return TOR_EINVAL;
@@ -1270,6 +1311,7 @@ int tor_eval_part(const void* O, int32_t n, int64_t ld, int32_t tier, const tor_
   Workspace* w = nullptr;
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
+  if (wants_check(opt)) TOR_TRY(check_input(w, O, nullptr, nullptr, 1, n, ld, s));
   TOR_TRY(ensure_cap(w, p.bytes));
   const size_t codes = (size_t)1 << k;
   const size_t c_lo = (size_t)part * codes / (size_t)nparts;
@@ -1340,6 +1382,7 @@ int tor_eval_batched(const void* O_packed, const int64_t* offsets, const int32_t
   Workspace* w = nullptr;
   TOR_TRY(get_ws(&w));
   hipStream_t s = (hipStream_t)stream;
+  if (wants_check(opt)) TOR_TRY(check_input(w, O_packed, offsets, n, batch, 0, 0, s));
   std::vector<int32_t> tier_of(batch);
   for (int k = 0; k < batch; ++k) tier_of[k] = tiers ? tiers[k] : TOR_AUTO;
   std::vector<double> pred;

@@ -453,6 +453,43 @@ hipError_t launch_stage(const double2* O, int n, int64_t ld, double2* Oi, hipStr
   return hipGetLastError();
 }
 
+// The input conventions the kernels rely on, checked on the device: every
+// entry finite, O Hermitian, and the block structure of Eq. 3 (O11 = conj
+// O00, O10 = conj O01).  One workgroup per instance; bad[inst] is set to 1
+// on any violation (it must be zero on entry).  offs == nullptr: a single
+// instance at O with leading dimension ld; else instance k at O + offs[k]
+// with leading dimension 2 ns[k].
+__global__ __launch_bounds__(256) void check_input_kernel(const double2* __restrict__ O,
+                                                          const int64_t* __restrict__ offs,
+                                                          const int32_t* __restrict__ ns, int n1, int64_t ld1,
+                                                          int32_t* __restrict__ bad) {
+  const int inst = blockIdx.x;
+  const int n = offs ? ns[inst] : n1;
+  const int64_t ld = offs ? 2 * (int64_t)n : ld1;
+  const double2* A = offs ? O + offs[inst] : O;
+  const int N2 = 2 * n;
+  bool ok = true;
+  for (int e = threadIdx.x; e < N2 * N2; e += 256) {
+    const int i = e / N2, j = e - (e / N2) * N2;
+    const double2 a = A[(int64_t)i * ld + j], t = A[(int64_t)j * ld + i];
+    ok = ok && isfinite(a.x) && isfinite(a.y) && a.x == t.x && a.y == -t.y;
+    if (i < n && j < n) {
+      const double2 d = A[(int64_t)(i + n) * ld + (j + n)];  // O11 = conj(O00)
+      const double2 c = A[(int64_t)(i + n) * ld + j];        // O10 = conj(O01)
+      const double2 b = A[(int64_t)i * ld + (j + n)];
+      ok = ok && d.x == a.x && d.y == -a.y && c.x == b.x && c.y == -b.y;
+    }
+  }
+  if (!ok) atomicOr(&bad[inst], 1);
+}
+
+hipError_t launch_check_input(const double2* O, const int64_t* offs, const int32_t* ns, int ninst, int n1, int64_t ld1,
+                              int32_t* bad, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(check_input_kernel, dim3(ninst), dim3(256), 0, s, O, offs, ns, n1, ld1, bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_kernel, dim3((count + 255) / 256), dim3(256), 0, s, p, count);

@@ -24,6 +24,13 @@ size_t acc_bytes(int tier);
 // (row 2a+u <-> block row a + u n), both triangles filled.
 hipError_t launch_stage(const double2* O, int n, int64_t ld, double2* Oi, hipStream_t s);
 
+// Check the input conventions of ninst instances (finite, Hermitian, the
+// block structure of Eq. 3): offs == nullptr for one instance at O (n1, ld1),
+// else device offs / ns per instance.  bad[k] (zeroed by the caller) becomes
+// 1 where instance k violates them.
+hipError_t launch_check_input(const double2* O, const int64_t* offs, const int32_t* ns, int ninst, int n1, int64_t ld1,
+                              int32_t* bad, hipStream_t s);
+
 // Zero `count` 32-bit words (a kernel, so the call is safe inside a captured graph).
 hipError_t launch_zero_words(uint32_t* p, int count, hipStream_t s);
 

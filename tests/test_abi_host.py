@@ -93,6 +93,12 @@ def test_c_client_links_and_checks_its_arguments_without_a_gpu():
     assert p.returncode == 1 and "cannot read" in p.stderr
 
 
+def test_input_error_has_its_own_message(L):
+    L.tor_strerror.restype = ctypes.c_char_p
+    msg = L.tor_strerror(-6).decode()
+    assert "Hermitian" in msg and msg != L.tor_strerror(-1).decode()
+
+
 def test_argument_checks_need_no_gpu(L):
     from paper_2009_01177_amd import _lib
     out = _lib.TorResultC()
