@@ -87,6 +87,21 @@ def _as_o(O):
     return O, O.shape[0] // 2
 
 
+def asymmetry(O) -> dict:
+    """How far O is from the conventions every Torontonian code here
+    assumes (reported, never repaired): the largest |O - O^H| entry, and
+    the largest deviations from the block structure of the sampling matrix
+    (Eq. 3: O11 = conj(O00), O10 = conj(O01)).  All zero for inputs built
+    by gbs_inputs."""
+    O, n = _as_o(O)
+    if n == 0:
+        return dict(hermitian=0.0, o11=0.0, o10=0.0)
+    herm = float(np.max(np.abs(O - O.conj().T)))
+    o11 = float(np.max(np.abs(O[n:, n:] - O[:n, :n].conj())))
+    o10 = float(np.max(np.abs(O[n:, :n] - O[:n, n:].conj())))
+    return dict(hermitian=herm, o11=o11, o10=o10)
+
+
 def _dptr(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
@@ -104,7 +119,9 @@ def max_threads() -> int:
 def tor(O, threads: int = 0, level_sums: bool = False) -> dict:
     """Tor(O) over all subsets (n <= 26), exactly as Fractions.
 
-    Returns dict(tor, abs_sum, kappa, min_det, max_term, levels?, threads).
+    Returns dict(tor, abs_sum, kappa, min_det, max_term, asymmetry, levels?,
+    threads); asymmetry reports (does not repair) O's deviations from
+    Hermitian and from the block structure of Eq. 3.
     Raises OracleError(ENOTPD) when I - O_Z is not positive definite for some Z.
     """
     lib = _load()
@@ -122,6 +139,7 @@ def tor(O, threads: int = 0, level_sums: bool = False) -> dict:
     out = dict(tor=t, abs_sum=a, min_det=_frac3(res.min_det), max_term=_frac3(res.max_term),
                threads=int(res.threads))
     out["kappa"] = float(a / abs(t)) if t != 0 else float("inf")
+    out["asymmetry"] = asymmetry(O)
     if level_sums:
         out["levels"] = [_frac3(lv[3 * m:3 * m + 3]) for m in range(n + 1)]
     return out

@@ -316,3 +316,27 @@ def test_input_symmetries_hold_exactly():
     assert np.array_equal(O, O.conj().T)
     assert np.array_equal(O[n:, n:], O[:n, :n].conj())
     assert np.array_equal(O[:n, n:], O[:n, n:].T)
+
+
+def test_asymmetry_is_reported_not_repaired():
+    """The oracle reports O's deviations from Hermitian and from the block
+    structure of Eq. 3 (O11 = conj O00, O10 = conj O01); it does not repair
+    them.  Built inputs report zeros; a planted deviation in one block is
+    reported at its own size in the blocks it breaks and nowhere else."""
+    O, _ = g.workload("n16_lossless")
+    n = O.shape[0] // 2
+    r = oracle.tor(g.random_instance(6, 11))
+    assert r["asymmetry"] == dict(hermitian=0.0, o11=0.0, o10=0.0)
+    assert oracle.asymmetry(O) == dict(hermitian=0.0, o11=0.0, o10=0.0)
+    P = O.copy()
+    P[0, 1] += 3e-9                                   # inside O00 only
+    a = oracle.asymmetry(P)
+    assert a["hermitian"] == pytest.approx(3e-9, rel=1e-6)
+    assert a["o11"] == pytest.approx(3e-9, rel=1e-6) and a["o10"] == 0.0
+    P = O.copy()
+    P[n + 2, 1] += 5e-7j                              # inside O10 only
+    a = oracle.asymmetry(P)
+    assert a["hermitian"] == pytest.approx(5e-7, rel=1e-6)
+    assert a["o10"] == pytest.approx(5e-7, rel=1e-6) and a["o11"] == 0.0
+    # the input itself is left as it was
+    assert P[n + 2, 1] != O[n + 2, 1]
