@@ -738,8 +738,11 @@ struct Leaf {
       wave_sync();
       {
         // children, in passes of K * 64 mode blocks; the last, partial pass
-        // uses only as many 64-item slices as it needs
-        constexpr int K = sizeof(R) == sizeof(double) ? 4 : 2;
+        // uses only as many 64-item slices as it needs.  K items per lane
+        // in flight: four in binary64, three in double- and quad-double (the
+        // fastest measured at n = 30: against two, DD 2.5% and QD 6.6%
+        // faster; four in QD, or in binary64 eight, are slower)
+        constexpr int K = sizeof(R) == sizeof(double) ? 4 : 3;
         const int S1 = S - 1;
         const DivBy db(S1 * (S1 + 1) / 2);
         const int tot = ns * db.d;
